@@ -1,0 +1,203 @@
+/*
+ * lor.h -- C-ABI of liblor.so: longest overlap region between DNA sequences
+ * on MI355X (gfx950).
+ *
+ * The library builds the suffix array (SA) of a separator-joined DNA text with
+ * DC3 (Section III, Steps 1-3), its LCP array (Section III, Table IV), a range
+ * minimum structure over the LCP (Section III, RMQ), and scans the LCP for the
+ * longest region shared by two different sequences (Section III, problem
+ * statement). Every stage runs as hand-written HIP kernels.
+ *
+ * Conventions for every entry point:
+ *  - Device pointers point to memory of the current HIP device. The library
+ *    never allocates device memory: the caller owns every buffer, including a
+ *    workspace whose size the matching *_workspace() query returns.
+ *  - `hip_stream` is a hipStream_t (NULL = the null stream). Work is enqueued
+ *    on it in order. Entry points whose result is a host value synchronise the
+ *    stream before returning; the others return once work is enqueued, except
+ *    lor_build_sa and lor_suffix_array_i32, which read one word back per DC3
+ *    level (recursion depth depends on the text) and so return after the work.
+ *  - Argument errors are detected on the host before any work is enqueued and
+ *    leave outputs untouched. No function throws across the ABI.
+ *  - Sizes: joined length N = total bases + number of sequences must satisfy
+ *    N <= 2^31 - 1 (int32 SA/LCP).
+ *  - Calls that share a workspace must not overlap; calls with distinct
+ *    workspaces may run concurrently on distinct streams.
+ */
+#ifndef LOR_H
+#define LOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lor_status;
+enum {
+    LOR_OK = 0,
+    LOR_EINVAL = 1,      /* bad pointer, size, offsets or mode */
+    LOR_EALPHABET = 2,   /* an input base is not in 0..3 */
+    LOR_ETOOLARGE = 3,   /* joined length would exceed 2^31 - 1 */
+    LOR_EWORKSPACE = 4,  /* workspace smaller than the size query returned */
+    LOR_EHIP = 5,        /* a HIP runtime call failed (see lor_last_error) */
+    LOR_ESTALE = 6       /* an RMQ handle does not match the arrays passed */
+};
+
+/* Static description of a status code. */
+const char *lor_status_string(lor_status s);
+/* Detail of the last error raised on the calling thread (thread-local, static storage). */
+const char *lor_last_error(void);
+/* ABI version, currently 1. */
+int32_t lor_version(void);
+
+/* ------------------------------------------------------------ suffix array
+ * Suffix array of the joined text (Section III, Table I; DC3 Steps 1-3).
+ *
+ * seqs    : device uint8, the sequences concatenated without separators, each
+ *           base coded A=0, C=1, G=2, T=3 (the order of Table I).
+ * offsets : HOST int64[num_seqs + 1]; sequence j is seqs[offsets[j] ..
+ *           offsets[j+1]); offsets[0] = 0 and non-decreasing. Empty sequences
+ *           are allowed.
+ * num_seqs: 1 .. 251 (separators 4..254).
+ * The joined text places after sequence j its own separator symbol 4 + j, so
+ * every separator is unique and sorts after every base; its length is
+ * N = offsets[num_seqs] + num_seqs and position p of the joined text is a
+ * "joined position". Because the last symbol is unique, no suffix is a prefix
+ * of another and the SA is unique.
+ * joined_out: device uint8[N] or NULL; receives the joined text.
+ * sa_out  : device int32[N]; receives SA, sa_out[r] = joined position of the
+ *           suffix of rank r (0-based).
+ * ws      : device workspace of at least lor_build_sa_workspace() bytes,
+ *           256-byte aligned.
+ * A base outside 0..3 returns LOR_EALPHABET (detected on the device; sa_out
+ * is then unspecified).
+ */
+size_t lor_build_sa_workspace(int64_t total_bases, int32_t num_seqs);
+lor_status lor_build_sa(const uint8_t *seqs, const int64_t *offsets, int32_t num_seqs,
+                        uint8_t *joined_out, int32_t *sa_out,
+                        void *ws, size_t ws_bytes, void *hip_stream);
+
+/* DC3 core on an integer text (Section III, Steps 1-3, recursion on the
+ * text of triple names). text: device int32[n] with every symbol in
+ * 1 .. alphabet_max; positions at or past n read as 0, below every symbol
+ * (the paper's zero padding of the last triples, e.g. "C00"), so a suffix
+ * that is a prefix of another sorts first. sa_out: device int32[n].
+ * 1 <= n <= 2^31 - 1, 1 <= alphabet_max <= 2^31 - 2. Symbols outside the
+ * range give an unspecified order (not detected). */
+size_t lor_suffix_array_workspace(int64_t n);
+lor_status lor_suffix_array_i32(const int32_t *text, int64_t n, int32_t alphabet_max,
+                                int32_t *sa_out, void *ws, size_t ws_bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------- LCP
+ * LCP array (Section III, Table IV): lcp_out[0] = 0 and lcp_out[r] = length
+ * of the longest common prefix of the suffixes sa[r-1] and sa[r] of
+ * text[0..n). Computed with the permuted-LCP method: Phi[sa[r]] = sa[r-1],
+ * PLCP[i] = lcp(i, Phi[i]) using PLCP[i] >= PLCP[i-1] - 1 (Kasai et al.),
+ * LCP[r] = PLCP[sa[r]].
+ * text: device uint8[n] (any byte values; the joined text of lor_build_sa);
+ * sa: device int32[n], a permutation of 0..n-1 (the suffix array of text);
+ * lcp_out: device int32[n]; isa_out: device int32[n] or NULL, receives the
+ * inverse permutation isa_out[sa[r]] = r (Table III, 0-based).
+ * ws: at least lor_build_lcp_workspace(n) bytes. */
+size_t lor_build_lcp_workspace(int64_t n);
+lor_status lor_build_lcp(const uint8_t *text, int64_t n, const int32_t *sa,
+                         int32_t *lcp_out, int32_t *isa_out,
+                         void *ws, size_t ws_bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------- RMQ
+ * Range minimum over the LCP array (Section III, RMQ definition; the lcp of
+ * two suffixes is the minimum of the LCP between their ranks). Built as a
+ * sparse table: level k (1 <= k <= levels = floor(log2 n)) holds, for every
+ * i with i + 2^k <= n, the minimum of LCP[i .. i + 2^k). Level 0 is the LCP
+ * array itself and is not copied. The table memory is caller-owned; the
+ * handle is plain data that records where the levels are. */
+typedef struct {
+    int32_t *table;      /* device memory holding levels 1..levels */
+    int64_t n;           /* length of the LCP array */
+    int32_t levels;      /* floor(log2 n), 0 when n < 2 */
+    int32_t reserved;
+} lor_rmq;
+
+/* Bytes of levels 1..floor(log2 n). */
+size_t lor_rmq_bytes(int64_t n);
+lor_status lor_rmq_build(const int32_t *lcp, int64_t n, void *table, size_t table_bytes,
+                         lor_rmq *out, void *hip_stream);
+
+/* Batched queries, one result per query k < nq:
+ *  mode 0 (rank ranges): lo = qi[k], hi = qj[k], 0 <= lo <= hi < n;
+ *         min_out[k] = min LCP[lo..hi]; argmin_out[k] (nullable) = leftmost
+ *         position of that minimum (the RMQ of Section III returns a position).
+ *  mode 1 (suffix pairs): i = qi[k], j = qj[k] are text positions in 0..n-1;
+ *         min_out[k] = lcp of suffixes i and j, i.e. n - i when i == j and
+ *         otherwise min LCP over ranks (min(isa[i],isa[j]), max(isa[i],isa[j])]
+ *         (Section III, lcp as a range minimum). isa is required;
+ *         argmin_out (nullable) receives the rank of that minimum.
+ * A query whose indices fall outside 0..n-1 (or lo > hi in mode 0) yields
+ * -1 in both outputs and is otherwise ignored.
+ * lcp must be the array the handle was built from; a handle with a different
+ * n returns LOR_ESTALE. */
+lor_status lor_rmq_query(const lor_rmq *rmq, const int32_t *lcp, const int32_t *isa, int32_t mode,
+                         const int32_t *qi, const int32_t *qj, int64_t nq,
+                         int32_t *min_out, int32_t *argmin_out, void *hip_stream);
+
+/* ------------------------------------------------------- longest overlap
+ * Longest overlap region (Section III problem statement): the longest
+ * substring that occurs in two different sequences, found as the largest
+ * LCP between rank-adjacent suffixes that start in different sequences
+ * (unique separators stop every such common prefix inside both sequences).
+ * Among all pairs of joined positions (p, q), p < q, in different
+ * sequences whose suffixes share that many symbols, the lexicographically
+ * smallest is reported (for two sequences: smallest offset in the first,
+ * then smallest offset in the second).
+ * sa, lcp: device int32[n] of the joined text built from `offsets`
+ * (host int64[num_seqs+1], as in lor_build_sa). Result on the host.
+ * length == 0 reports -1 for the sequences and offsets.
+ * ws: at least lor_longest_overlap_workspace(n, num_seqs) bytes.
+ * Synchronises hip_stream. */
+typedef struct {
+    int64_t length;
+    int32_t seq_p, seq_q;     /* sequence indices, seq_p < seq_q not implied */
+    int64_t off_p, off_q;     /* offsets inside their own sequences */
+} lor_overlap;
+
+size_t lor_longest_overlap_workspace(int64_t n, int32_t num_seqs);
+lor_status lor_longest_overlap(const int32_t *sa, const int32_t *lcp, int64_t n,
+                               const int64_t *offsets, int32_t num_seqs,
+                               lor_overlap *out_host, void *ws, size_t ws_bytes, void *hip_stream);
+
+/* ------------------------------------------------------------ radix sort
+ * Stable LSD radix sort of (key, value) pairs by key bits [bit_lo, bit_hi)
+ * (Section IV: radix sort from the least to the most significant digit, the
+ * sort DC3 uses for sample and non-sample suffixes). Digits of up to 8 bits
+ * are ranked per tile with wavefront ballots and scattered through LDS.
+ * keys/vals: device arrays of n entries, sorted in place (the workspace holds
+ * the second buffers). 0 <= bit_lo < bit_hi <= 32 (u32) or 64 (u64).
+ * ws: at least lor_sort_pairs_workspace(n, key_bytes) bytes (key_bytes 4|8). */
+size_t lor_sort_pairs_workspace(int64_t n, int32_t key_bytes);
+lor_status lor_sort_pairs_u32(uint32_t *keys, uint32_t *vals, int64_t n, int32_t bit_lo, int32_t bit_hi,
+                              void *ws, size_t ws_bytes, void *hip_stream);
+lor_status lor_sort_pairs_u64(uint64_t *keys, uint32_t *vals, int64_t n, int32_t bit_lo, int32_t bit_hi,
+                              void *ws, size_t ws_bytes, void *hip_stream);
+
+/* --------------------------------------------------------- kernel timing
+ * Optional per-kernel timing with HIP events recorded on the launch stream
+ * around every launch of the named kernel families. Disabled by default.
+ * lor_timing_read fills up to `cap` records and returns how many families
+ * were timed; it synchronises each pending event. Not thread-safe. */
+typedef struct {
+    char name[32];          /* kernel family */
+    int64_t launches;
+    double ms;              /* summed event-measured duration */
+    double bytes;           /* summed algorithmic bytes (model in the design notes) */
+} lor_timing;
+
+void lor_timing_enable(int32_t on);
+void lor_timing_reset(void);
+int32_t lor_timing_read(lor_timing *out, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LOR_H */

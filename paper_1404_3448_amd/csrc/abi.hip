@@ -1,0 +1,399 @@
+// C-ABI entry points of liblor.so: argument checks, workspace carving, the
+// per-thread error text and the optional kernel-family timing registry.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "lor_internal.hpp"
+
+namespace lor {
+
+namespace {
+thread_local char g_err[512] = "";
+
+struct Pending {
+    hipEvent_t a, b;
+    int family;
+    double bytes;
+};
+struct FamilyStat {
+    int64_t launches = 0;
+    double ms = 0;
+    double bytes = 0;
+};
+bool g_timing = false;
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_event_pool;
+FamilyStat g_stats[F_NUM];
+const char *kFamilyNames[F_NUM] = {"join", "sample_keys", "radix_count", "radix_scan", "radix_scatter",
+                                   "naming", "rank_scatter", "merge_records", "nonsample", "merge_partition",
+                                   "merge", "phi", "plcp", "lcp_permute", "sparse_table", "rmq_query",
+                                   "overlap_scan", "misc"};
+
+hipEvent_t take_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void drain_pending() {
+    for (Pending &p : g_pending) {
+        float ms = 0;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            g_stats[p.family].launches += 1;
+            g_stats[p.family].ms += ms;
+            g_stats[p.family].bytes += p.bytes;
+        }
+        g_event_pool.push_back(p.a);
+        g_event_pool.push_back(p.b);
+    }
+    g_pending.clear();
+}
+}  // namespace
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+bool timing_on() { return g_timing; }
+
+int timing_begin(hipStream_t s, Family f, double bytes) {
+    if (g_pending.size() > 100000) drain_pending();
+    Pending p;
+    p.a = take_event();
+    p.b = take_event();
+    p.family = f;
+    p.bytes = bytes;
+    if (!p.a || !p.b) return -1;
+    (void)hipEventRecord(p.a, s);
+    g_pending.push_back(p);
+    return (int)g_pending.size() - 1;
+}
+
+void timing_end(int token, hipStream_t s) {
+    if (token >= 0 && token < (int)g_pending.size()) (void)hipEventRecord(g_pending[token].b, s);
+}
+
+}  // namespace lor
+
+using namespace lor;
+
+namespace {
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+lor_status check_ws(void *ws, size_t ws_bytes, size_t need) {
+    if (need && !ws) {
+        set_error("workspace pointer is NULL");
+        return LOR_EINVAL;
+    }
+    if (ws && !aligned(ws, 256)) {
+        set_error("workspace must be 256-byte aligned");
+        return LOR_EINVAL;
+    }
+    if (ws_bytes < need) {
+        set_error("workspace of %zu bytes, %zu needed", ws_bytes, need);
+        return LOR_EWORKSPACE;
+    }
+    return LOR_OK;
+}
+
+lor_status check_offsets(const int64_t *offsets, int32_t num_seqs, int64_t *N) {
+    if (!offsets) {
+        set_error("offsets is NULL");
+        return LOR_EINVAL;
+    }
+    if (num_seqs < 1 || num_seqs > kMaxSeqs) {
+        set_error("num_seqs %d outside 1..%d", num_seqs, kMaxSeqs);
+        return LOR_EINVAL;
+    }
+    if (offsets[0] != 0) {
+        set_error("offsets[0] must be 0");
+        return LOR_EINVAL;
+    }
+    for (int j = 0; j < num_seqs; ++j) {
+        if (offsets[j + 1] < offsets[j]) {
+            set_error("offsets decrease at %d", j);
+            return LOR_EINVAL;
+        }
+    }
+    const int64_t total = offsets[num_seqs];
+    if (total > (int64_t)INT32_MAX - num_seqs) {
+        set_error("joined length %lld exceeds 2^31-1", (long long)(total + num_seqs));
+        return LOR_ETOOLARGE;
+    }
+    *N = total + num_seqs;
+    return LOR_OK;
+}
+
+Arena arena_after_header(void *ws, size_t ws_bytes) {
+    Arena ar;
+    ar.base = static_cast<char *>(ws);
+    ar.cap = ws_bytes;
+    ar.top = kHeaderBytes;
+    ar.high = ar.top;
+    return ar;
+}
+
+size_t sa_bytes(int64_t N, bool need_joined) {
+    size_t b = kHeaderBytes + 256;
+    if (need_joined) b += ((size_t)N + 255) & ~size_t(255);
+    return b + dc3_workspace_bound((uint64_t)N);
+}
+
+}  // namespace
+
+namespace {
+template <typename K>
+lor_status sort_pairs(K *keys, uint32_t *vals, int64_t n, int32_t bit_lo, int32_t bit_hi, void *ws,
+                             size_t ws_bytes, void *hip_stream) {
+    const int kb = (int)sizeof(K) * 8;
+    if (n < 0 || n > INT32_MAX || bit_lo < 0 || bit_hi > kb || bit_lo >= bit_hi || (n > 0 && (!keys || !vals))) {
+        set_error("invalid sort arguments");
+        return LOR_EINVAL;
+    }
+    LOR_TRY(check_ws(ws, ws_bytes, lor_sort_pairs_workspace(n, (int32_t)sizeof(K))));
+    hipStream_t s = (hipStream_t)hip_stream;
+    Arena ar = arena_after_header(ws, ws_bytes);
+    K *k1;
+    uint32_t *v1, *counts;
+    LOR_TAKE(ar, K, (size_t)n, k1);
+    LOR_TAKE(ar, uint32_t, (size_t)n, v1);
+    LOR_TAKE(ar, uint32_t, radix_counts_words((uint64_t)n), counts);
+    bool alt = false;
+    LOR_TRY(radix_sort<K>(keys, vals, k1, v1, (uint32_t)n, bit_lo, bit_hi, counts, s, &alt));
+    if (alt) {
+        LOR_HIP(hipMemcpyAsync(keys, k1, (size_t)n * sizeof(K), hipMemcpyDeviceToDevice, s));
+        LOR_HIP(hipMemcpyAsync(vals, v1, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+    }
+    return LOR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lor_status_string(lor_status s) {
+    switch (s) {
+        case LOR_OK: return "ok";
+        case LOR_EINVAL: return "invalid argument";
+        case LOR_EALPHABET: return "base outside A,C,G,T (0..3)";
+        case LOR_ETOOLARGE: return "joined text longer than 2^31-1";
+        case LOR_EWORKSPACE: return "workspace too small";
+        case LOR_EHIP: return "HIP runtime error";
+        case LOR_ESTALE: return "RMQ handle does not match the arrays";
+        default: return "unknown status";
+    }
+}
+
+const char *lor_last_error(void) { return g_err; }
+
+int32_t lor_version(void) { return 1; }
+
+size_t lor_build_sa_workspace(int64_t total_bases, int32_t num_seqs) {
+    if (total_bases < 0 || num_seqs < 1 || total_bases + num_seqs > INT32_MAX) return 0;
+    return sa_bytes(total_bases + num_seqs, true);
+}
+
+lor_status lor_build_sa(const uint8_t *seqs, const int64_t *offsets, int32_t num_seqs, uint8_t *joined_out,
+                        int32_t *sa_out, void *ws, size_t ws_bytes, void *hip_stream) {
+    int64_t N = 0;
+    LOR_TRY(check_offsets(offsets, num_seqs, &N));
+    if (!sa_out || (!seqs && offsets[num_seqs] > 0)) {
+        set_error("NULL seqs or sa_out");
+        return LOR_EINVAL;
+    }
+    if (joined_out && !aligned(joined_out, 4)) {
+        set_error("joined_out must be 4-byte aligned");
+        return LOR_EINVAL;
+    }
+    LOR_TRY(check_ws(ws, ws_bytes, sa_bytes(N, joined_out == nullptr)));
+    hipStream_t s = (hipStream_t)hip_stream;
+    Arena ar = arena_after_header(ws, ws_bytes);
+    uint32_t *hdr = static_cast<uint32_t *>(ws);
+    uint8_t *joined = joined_out;
+    if (!joined) LOR_TAKE(ar, uint8_t, (size_t)N, joined);
+    LOR_TRY(zero_words(hdr, 16, s));
+    LOR_TRY(join_text(seqs, offsets, num_seqs, joined, hdr, s));
+    // symbols are byte + 1: bases 1..4, separators 5..4+num_seqs
+    return dc3_u8(joined, (uint32_t)N, 4u + (uint32_t)num_seqs, sa_out, ar, hdr, s);
+}
+
+size_t lor_suffix_array_workspace(int64_t n) {
+    if (n < 0 || n > INT32_MAX) return 0;
+    return sa_bytes(n, false);
+}
+
+lor_status lor_suffix_array_i32(const int32_t *text, int64_t n, int32_t alphabet_max, int32_t *sa_out, void *ws,
+                                size_t ws_bytes, void *hip_stream) {
+    if (n < 0 || n > INT32_MAX) {
+        set_error("n = %lld outside 0..2^31-1", (long long)n);
+        return n < 0 ? LOR_EINVAL : LOR_ETOOLARGE;
+    }
+    if (n > 0 && (!text || !sa_out)) {
+        set_error("NULL text or sa_out");
+        return LOR_EINVAL;
+    }
+    if (alphabet_max < 1 || alphabet_max > INT32_MAX - 1) {
+        set_error("alphabet_max %d outside 1..2^31-2", alphabet_max);
+        return LOR_EINVAL;
+    }
+    LOR_TRY(check_ws(ws, ws_bytes, sa_bytes(n, false)));
+    hipStream_t s = (hipStream_t)hip_stream;
+    Arena ar = arena_after_header(ws, ws_bytes);
+    uint32_t *hdr = static_cast<uint32_t *>(ws);
+    LOR_TRY(zero_words(hdr, 16, s));
+    return dc3_i32(text, (uint32_t)n, (uint32_t)alphabet_max, sa_out, ar, hdr, s);
+}
+
+size_t lor_build_lcp_workspace(int64_t n) {
+    if (n < 0 || n > INT32_MAX) return 0;
+    return kHeaderBytes + 256 + lcp_workspace((uint64_t)n);
+}
+
+lor_status lor_build_lcp(const uint8_t *text, int64_t n, const int32_t *sa, int32_t *lcp_out, int32_t *isa_out,
+                         void *ws, size_t ws_bytes, void *hip_stream) {
+    if (n < 0 || n > INT32_MAX) {
+        set_error("n = %lld outside 0..2^31-1", (long long)n);
+        return n < 0 ? LOR_EINVAL : LOR_ETOOLARGE;
+    }
+    if (n > 0 && (!text || !sa || !lcp_out)) {
+        set_error("NULL text, sa or lcp_out");
+        return LOR_EINVAL;
+    }
+    LOR_TRY(check_ws(ws, ws_bytes, lor_build_lcp_workspace(n)));
+    Arena ar = arena_after_header(ws, ws_bytes);
+    return lcp_build(text, (uint32_t)n, sa, lcp_out, isa_out, ar, (hipStream_t)hip_stream);
+}
+
+size_t lor_rmq_bytes(int64_t n) {
+    if (n < 2 || n > INT32_MAX) return 0;
+    const int levels = bits_for((uint64_t)n) - 1;
+    return (size_t)rmq_level_offset((uint64_t)n, levels + 1) * sizeof(int32_t);
+}
+
+lor_status lor_rmq_build(const int32_t *lcp, int64_t n, void *table, size_t table_bytes, lor_rmq *out,
+                         void *hip_stream) {
+    if (!out || n < 0 || n > INT32_MAX || (n > 0 && !lcp)) {
+        set_error("invalid RMQ build arguments");
+        return LOR_EINVAL;
+    }
+    const size_t need = lor_rmq_bytes(n);
+    if (need && (!table || !aligned(table, 4))) {
+        set_error("RMQ table NULL or misaligned");
+        return LOR_EINVAL;
+    }
+    if (table_bytes < need) {
+        set_error("RMQ table of %zu bytes, %zu needed", table_bytes, need);
+        return LOR_EWORKSPACE;
+    }
+    const int levels = n >= 2 ? bits_for((uint64_t)n) - 1 : 0;
+    LOR_TRY(rmq_build_levels(lcp, (uint32_t)n, static_cast<int32_t *>(table), levels, (hipStream_t)hip_stream));
+    out->table = static_cast<int32_t *>(table);
+    out->n = n;
+    out->levels = levels;
+    out->reserved = 0;
+    return LOR_OK;
+}
+
+lor_status lor_rmq_query(const lor_rmq *rmq, const int32_t *lcp, const int32_t *isa, int32_t mode,
+                         const int32_t *qi, const int32_t *qj, int64_t nq, int32_t *min_out, int32_t *argmin_out,
+                         void *hip_stream) {
+    if (!rmq || mode < 0 || mode > 1 || nq < 0 || nq > INT32_MAX) {
+        set_error("invalid RMQ query arguments");
+        return LOR_EINVAL;
+    }
+    if (nq == 0) return LOR_OK;
+    if (!lcp || !qi || !qj || !min_out || (mode == 1 && !isa)) {
+        set_error("NULL query array");
+        return LOR_EINVAL;
+    }
+    const int expect = rmq->n >= 2 ? bits_for((uint64_t)rmq->n) - 1 : 0;
+    if (rmq->n < 1 || rmq->n > INT32_MAX || rmq->levels != expect || (expect > 0 && !rmq->table)) {
+        set_error("RMQ handle does not describe a built table");
+        return LOR_ESTALE;
+    }
+    return rmq_queries(rmq->table, (uint32_t)rmq->n, rmq->levels, lcp, isa, mode, qi, qj, (uint32_t)nq, min_out,
+                       argmin_out, (hipStream_t)hip_stream);
+}
+
+size_t lor_longest_overlap_workspace(int64_t n, int32_t num_seqs) {
+    (void)num_seqs;
+    if (n < 0 || n > INT32_MAX) return 0;
+    return kHeaderBytes + 512 + overlap_workspace((uint64_t)n);
+}
+
+lor_status lor_longest_overlap(const int32_t *sa, const int32_t *lcp, int64_t n, const int64_t *offsets,
+                               int32_t num_seqs, lor_overlap *out_host, void *ws, size_t ws_bytes,
+                               void *hip_stream) {
+    int64_t N = 0;
+    LOR_TRY(check_offsets(offsets, num_seqs, &N));
+    if (!out_host || N != n || (n > 0 && (!sa || !lcp))) {
+        set_error("overlap: NULL array/result or n != joined length of offsets");
+        return LOR_EINVAL;
+    }
+    LOR_TRY(check_ws(ws, ws_bytes, lor_longest_overlap_workspace(n, num_seqs)));
+    SeqStarts st;
+    st.k = num_seqs;
+    for (int j = 0; j <= num_seqs; ++j) st.start[j] = (int32_t)(offsets[j] + j);
+    Arena ar = arena_after_header(ws, ws_bytes);
+    int64_t r[5];
+    LOR_TRY(overlap_scan(sa, lcp, (uint32_t)n, st, ar, (hipStream_t)hip_stream, r));
+    out_host->length = r[0];
+    out_host->seq_p = (int32_t)r[1];
+    out_host->off_p = r[2];
+    out_host->seq_q = (int32_t)r[3];
+    out_host->off_q = r[4];
+    return LOR_OK;
+}
+
+size_t lor_sort_pairs_workspace(int64_t n, int32_t key_bytes) {
+    if (n < 0 || n > INT32_MAX || (key_bytes != 4 && key_bytes != 8)) return 0;
+    return kHeaderBytes + 1024 + (size_t)n * (size_t)(key_bytes + 4) + radix_counts_words((uint64_t)n) * 4;
+}
+
+lor_status lor_sort_pairs_u32(uint32_t *keys, uint32_t *vals, int64_t n, int32_t bit_lo, int32_t bit_hi, void *ws,
+                              size_t ws_bytes, void *hip_stream) {
+    return sort_pairs<uint32_t>(keys, vals, n, bit_lo, bit_hi, ws, ws_bytes, hip_stream);
+}
+
+lor_status lor_sort_pairs_u64(uint64_t *keys, uint32_t *vals, int64_t n, int32_t bit_lo, int32_t bit_hi, void *ws,
+                              size_t ws_bytes, void *hip_stream) {
+    return sort_pairs<uint64_t>(keys, vals, n, bit_lo, bit_hi, ws, ws_bytes, hip_stream);
+}
+
+void lor_timing_enable(int32_t on) { g_timing = on != 0; }
+
+void lor_timing_reset(void) {
+    drain_pending();
+    for (auto &f : g_stats) f = FamilyStat();
+}
+
+int32_t lor_timing_read(lor_timing *out, int32_t cap) {
+    drain_pending();
+    int32_t w = 0;
+    for (int f = 0; f < F_NUM; ++f) {
+        if (!g_stats[f].launches) continue;
+        if (out && w < cap) {
+            memset(&out[w], 0, sizeof(lor_timing));
+            strncpy(out[w].name, kFamilyNames[f], sizeof(out[w].name) - 1);
+            out[w].launches = g_stats[f].launches;
+            out[w].ms = g_stats[f].ms;
+            out[w].bytes = g_stats[f].bytes;
+        }
+        ++w;
+    }
+    return w;
+}
+
+}  // extern "C"

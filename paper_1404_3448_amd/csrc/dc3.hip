@@ -1,0 +1,684 @@
+// DC3 (skew) suffix sorting on gfx950, Section III Steps 1-3.
+//
+// One level on a text t[0..n) whose symbols are >= 1 (positions >= n read 0):
+//   Step 1  sample positions are i mod 3 in {1, 2}; when n mod 3 == 1 the
+//           padding-only position n joins the mod-1 class so that the last
+//           mod-1 triple is unique and the suffixes of R stop before R2.
+//           Each sample position gets the key of its triple
+//           (t_i, t_{i+1}, t_{i+2}); the keys are radix sorted, named in
+//           sorted order (a flag where a key differs from its predecessor,
+//           prefix-summed into 1-based names, as in Table II), and the names
+//           form the text R = R1 R2 (mod-1 block, then mod-2 block, each in
+//           position order). If a name repeats, DC3 recurses on R.
+//           "R-index" below is a position in R.
+//   Step 2  non-sample suffixes S_i (i mod 3 == 0) in order of
+//           (t_i, rank(S_{i+1})): take the sample order, keep mod-1 entries
+//           (whose predecessors are the mod-0 positions), stable-sort by t_i.
+//   Step 3  merge: a mod-1 suffix S_i against a mod-0 suffix S_j compares
+//           (t_i, rank(S_{i+1})) with (t_j, rank(S_{j+1})); a mod-2 suffix
+//           compares (t_i, t_{i+1}, rank(S_{i+2})) with
+//           (t_j, t_{j+1}, rank(S_{j+2})). rank() of a position >= n is 0.
+//
+// MI355X design notes: every step streams or gathers whole arrays in HBM;
+// the merge needs, per element, two symbols and one or two ranks from
+// random places. A streaming pass first builds one record per position
+// triple q = (t_3q..t_3q+3, rank(3q+1), rank(3q+2), rank(3q+4)); every merge
+// element (mod 0, 1 or 2) then needs exactly one record gather, and the
+// merge-path partitioning keeps each workgroup on a fixed output tile.
+#include "lor_internal.hpp"
+
+namespace lor {
+
+namespace {
+
+constexpr int kScanItems = 8;                         // consecutive items per thread in scan-emit kernels
+constexpr uint32_t kScanTile = kBlock * kScanItems;
+constexpr uint32_t kMaxScanGroups = 1024;
+constexpr int kMergeItems = 8;
+constexpr uint32_t kMergeTile = kBlock * kMergeItems; // outputs per merge workgroup
+
+struct Dims {
+    uint32_t n, n0, n1, n2, m, dummy;
+    __host__ __device__ uint32_t pos_of(uint32_t idx) const {
+        return idx < n0 ? 3u * idx + 1u : 3u * (idx - n0) + 2u;
+    }
+};
+
+Dims make_dims(uint32_t n) {
+    Dims d;
+    d.n = n;
+    d.n0 = (n + 2) / 3;
+    d.n1 = (n + 1) / 3;
+    d.n2 = n / 3;
+    d.m = d.n0 + d.n2;
+    d.dummy = d.n0 - d.n1;
+    return d;
+}
+
+template <typename CH> __device__ __forceinline__ uint32_t sym(const CH *t, uint32_t n, uint32_t i);
+template <> __device__ __forceinline__ uint32_t sym<uint8_t>(const uint8_t *t, uint32_t n, uint32_t i) {
+    return i < n ? (uint32_t)t[i] + 1u : 0u;
+}
+template <> __device__ __forceinline__ uint32_t sym<int32_t>(const int32_t *t, uint32_t n, uint32_t i) {
+    return i < n ? (uint32_t)t[i] : 0u;
+}
+
+__device__ __forceinline__ void group_tiles(uint32_t items, uint32_t groups, uint32_t g, uint32_t *t0,
+                                            uint32_t *t1) {
+    const uint32_t tiles = (items + kScanTile - 1) / kScanTile;
+    *t0 = (uint32_t)((uint64_t)tiles * g / groups);
+    *t1 = (uint32_t)((uint64_t)tiles * (g + 1) / groups);
+}
+
+uint32_t scan_groups(uint32_t items) {
+    uint32_t tiles = div_up(items, kScanTile);
+    if (tiles == 0) tiles = 1;
+    return tiles < kMaxScanGroups ? tiles : kMaxScanGroups;
+}
+
+// ---------------------------------------------------------------- join
+
+__global__ __launch_bounds__(kBlock) void k_join(const uint8_t *__restrict__ seqs, SeqStarts st,
+                                                 uint32_t N, uint8_t *__restrict__ out,
+                                                 uint32_t *__restrict__ err) {
+    __shared__ int32_t s_start[kMaxSeqs + 1];
+    for (int i = threadIdx.x; i <= st.k; i += kBlock) s_start[i] = st.start[i];
+    __syncthreads();
+    const int k = st.k;
+    uint32_t bad = 0;
+    const uint32_t stride = gridDim.x * kBlock * 4u;
+    for (uint32_t p0 = (blockIdx.x * kBlock + threadIdx.x) * 4u; p0 < N; p0 += stride) {
+        uint32_t word = 0;
+        int j = 0;
+        {   // sequence containing p0: largest j with start[j] <= p0
+            int lo = 0, hi = k - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if ((uint32_t)s_start[mid] <= p0) lo = mid; else hi = mid - 1;
+            }
+            j = lo;
+        }
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t p = p0 + u;
+            if (p >= N) break;
+            while ((uint32_t)s_start[j + 1] <= p) ++j;
+            uint32_t byte;
+            if (p == (uint32_t)s_start[j + 1] - 1u) {
+                byte = 4u + (uint32_t)j;
+            } else {
+                byte = seqs[p - (uint32_t)j];
+                bad |= byte > 3u;
+            }
+            word |= byte << (8 * u);
+        }
+        if (p0 + 4 <= N) {
+            *reinterpret_cast<uint32_t *>(out + p0) = word;   // p0 is a multiple of 4
+        } else {
+            for (uint32_t u = 0; p0 + u < N; ++u) out[p0 + u] = (uint8_t)(word >> (8 * u));
+        }
+    }
+    if (__any(bad) && dev::lane_id() == 0) atomicOr(err, 1u);
+}
+
+// ------------------------------------------------------- Step 1: keys
+
+// mode 0: packed triple key; mode 1: the single symbol at p + delta.
+template <typename CH, typename K>
+__global__ __launch_bounds__(kBlock) void k_sample_keys(const CH *__restrict__ t, Dims d, int b, int mode,
+                                                        int delta, K *__restrict__ keys,
+                                                        uint32_t *__restrict__ vals) {
+    for (uint32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < d.m; idx += gridDim.x * kBlock) {
+        const uint32_t p = d.pos_of(idx);
+        K key;
+        if (mode == 0) {
+            key = ((K)sym(t, d.n, p) << (2 * b)) | ((K)sym(t, d.n, p + 1) << b) | (K)sym(t, d.n, p + 2);
+        } else {
+            key = (K)sym(t, d.n, p + (uint32_t)delta);
+        }
+        keys[idx] = key;
+        vals[idx] = idx;
+    }
+}
+
+// keys[r] = symbol at pos(vals[r]) + delta (re-keying between LSD stages).
+template <typename CH>
+__global__ __launch_bounds__(kBlock) void k_rekey(const CH *__restrict__ t, Dims d, int delta,
+                                                  const uint32_t *__restrict__ vals,
+                                                  uint32_t *__restrict__ keys) {
+    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < d.m; r += gridDim.x * kBlock)
+        keys[r] = sym(t, d.n, d.pos_of(vals[r]) + (uint32_t)delta);
+}
+
+// ------------------------------------------------------ Step 1: naming
+
+// A sorted entry starts a new name when its triple differs from the
+// previous entry's. GATHER: compare triples read from the text (keys hold
+// only part of the triple).
+template <typename CH, typename K, bool GATHER>
+__device__ __forceinline__ bool starts_name(const CH *t, const Dims &d, const K *keys,
+                                            const uint32_t *vals, uint32_t r, K cur, K prev) {
+    if (r == 0) return true;
+    if (!GATHER) return cur != prev;
+    const uint32_t p = d.pos_of(vals[r]), q = d.pos_of(vals[r - 1]);
+    return sym(t, d.n, p) != sym(t, d.n, q) || sym(t, d.n, p + 1) != sym(t, d.n, q + 1) ||
+           sym(t, d.n, p + 2) != sym(t, d.n, q + 2);
+}
+
+template <typename CH, typename K, bool GATHER>
+__global__ __launch_bounds__(kBlock) void k_name_count(const CH *__restrict__ t, Dims d,
+                                                       const K *__restrict__ keys,
+                                                       const uint32_t *__restrict__ vals,
+                                                       uint32_t groups, uint32_t *__restrict__ counts) {
+    __shared__ uint32_t s_tmp[kBlock / kWave];
+    uint32_t t0, t1;
+    group_tiles(d.m, groups, blockIdx.x, &t0, &t1);
+    uint32_t c = 0;
+    for (uint32_t r = t0 * kScanTile + threadIdx.x; r < min(d.m, t1 * kScanTile); r += kBlock) {
+        const K cur = keys[r];
+        const K prev = r ? keys[r - 1] : cur;
+        c += starts_name<CH, K, GATHER>(t, d, keys, vals, r, cur, prev);
+    }
+    uint32_t tot;
+    dev::block_exclusive_sum(c, s_tmp, &tot);
+    if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+}
+
+template <typename CH, typename K, bool GATHER>
+__global__ __launch_bounds__(kBlock) void k_name_write(const CH *__restrict__ t, Dims d,
+                                                       const K *__restrict__ keys,
+                                                       const uint32_t *__restrict__ vals,
+                                                       uint32_t groups, const uint32_t *__restrict__ counts,
+                                                       int32_t *__restrict__ R) {
+    __shared__ uint32_t s_tmp[kBlock / kWave];
+    uint32_t t0, t1;
+    group_tiles(d.m, groups, blockIdx.x, &t0, &t1);
+    uint32_t base = counts[blockIdx.x];
+    for (uint32_t tile = t0; tile < t1; ++tile) {
+        const uint32_t r0 = tile * kScanTile + threadIdx.x * kScanItems;
+        bool f[kScanItems];
+        uint32_t c = 0;
+        K prev = (r0 > 0 && r0 < d.m) ? keys[r0 - 1] : K(0);
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint32_t r = r0 + i;
+            f[i] = false;
+            if (r < d.m) {
+                const K cur = keys[r];
+                f[i] = starts_name<CH, K, GATHER>(t, d, keys, vals, r, cur, prev);
+                prev = cur;
+            }
+            c += f[i];
+        }
+        uint32_t tot;
+        uint32_t name = base + dev::block_exclusive_sum(c, s_tmp, &tot);
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint32_t r = r0 + i;
+            if (r < d.m) {
+                name += f[i];
+                const uint32_t ri = vals[r];
+                if (ri < d.m) R[ri] = (int32_t)name;
+            }
+        }
+        base += tot;
+    }
+}
+
+// rank12[sa12[r]] = r + 1
+__global__ __launch_bounds__(kBlock) void k_rank_from_sa(const int32_t *__restrict__ sa12, uint32_t m,
+                                                         int32_t *__restrict__ rank12) {
+    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < m; r += gridDim.x * kBlock)
+    {
+        const uint32_t ri = (uint32_t)sa12[r];
+        if (ri < m) rank12[ri] = (int32_t)(r + 1);
+    }
+}
+
+// ----------------------------------------------- comparison records
+
+__device__ __forceinline__ uint32_t rank_at(const int32_t *rank12, const Dims &d, uint32_t p) {
+    if (p >= d.n) return 0u;
+    const uint32_t ri = (p % 3u == 1u) ? p / 3u : d.n0 + p / 3u;
+    return (uint32_t)rank12[ri];
+}
+
+// Record of triple q: symbols t_{3q..3q+3}, ranks of 3q+1, 3q+2, 3q+4.
+// u8 texts: one uint4 {c0|c1<<8|c2<<16|c3<<24, r1, r2, r4}; symbols are
+// byte + 1 <= 255 so each fits a byte (0 = past the end).
+// i32 texts: two uint4 {c0, c1, c2, c3}, {r1, r2, r4, 0}.
+template <typename CH> struct Rec;
+template <> struct Rec<uint8_t> { uint4 a; };
+template <> struct Rec<int32_t> { uint4 a, b; };
+
+template <typename CH>
+__global__ __launch_bounds__(kBlock) void k_records(const CH *__restrict__ t, Dims d,
+                                                    const int32_t *__restrict__ rank12,
+                                                    Rec<CH> *__restrict__ rec) {
+    const uint32_t nq = d.n0 + 1;
+    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < nq; q += gridDim.x * kBlock) {
+        const uint32_t p = 3u * q;
+        const uint32_t c0 = sym(t, d.n, p), c1 = sym(t, d.n, p + 1), c2 = sym(t, d.n, p + 2),
+                       c3 = sym(t, d.n, p + 3);
+        const uint32_t r1 = rank_at(rank12, d, p + 1), r2 = rank_at(rank12, d, p + 2),
+                       r4 = rank_at(rank12, d, p + 4);
+        Rec<CH> x;
+        if constexpr (sizeof(CH) == 1) {
+            x.a = make_uint4(c0 | (c1 << 8) | (c2 << 16) | (c3 << 24), r1, r2, r4);
+        } else {
+            x.a = make_uint4(c0, c1, c2, c3);
+            x.b = make_uint4(r1, r2, r4, 0u);
+        }
+        rec[q] = x;
+    }
+}
+
+// Comparison view of one merge element: c0, c1 symbols, r = rank used
+// against mod-0 elements (mod 1: rank(i+1); mod 2: rank(i+2)); for mod-0
+// elements r = rank(j+1) and r2 = rank(j+2). cls = position mod 3.
+struct Key4 {
+    uint32_t c0, c1, r, r2cls;   // r2cls: mod-0 elements hold rank(j+2); others hold their class
+};
+
+template <typename CH> __device__ __forceinline__ Key4 key_of(const Rec<CH> *rec, uint32_t pos);
+
+__device__ __forceinline__ Key4 make_key(uint32_t cls, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                         uint32_t r1, uint32_t r2, uint32_t r4) {
+    Key4 k;
+    if (cls == 0) { k.c0 = c0; k.c1 = c1; k.r = r1; k.r2cls = r2; }
+    else if (cls == 1) { k.c0 = c1; k.c1 = c2; k.r = r2; k.r2cls = 1; }
+    else { k.c0 = c2; k.c1 = c3; k.r = r4; k.r2cls = 2; }
+    return k;
+}
+
+// Positions always come from a permutation of 0..n-1; pos is clamped to n-1
+// by the callers so that a broken permutation cannot read past the records.
+template <> __device__ __forceinline__ Key4 key_of<uint8_t>(const Rec<uint8_t> *rec, uint32_t pos) {
+    const uint4 a = rec[pos / 3u].a;
+    return make_key(pos % 3u, a.x & 255u, (a.x >> 8) & 255u, (a.x >> 16) & 255u, a.x >> 24, a.y, a.z, a.w);
+}
+template <> __device__ __forceinline__ Key4 key_of<int32_t>(const Rec<int32_t> *rec, uint32_t pos) {
+    const Rec<int32_t> x = rec[pos / 3u];
+    return make_key(pos % 3u, x.a.x, x.a.y, x.a.z, x.a.w, x.b.x, x.b.y, x.b.z);
+}
+
+// Is sample suffix b smaller than mod-0 suffix a? (Step 3 rules.)
+__device__ __forceinline__ bool sample_less(const Key4 &b, const Key4 &a) {
+    if (b.c0 != a.c0) return b.c0 < a.c0;
+    if (b.r2cls == 1) return b.r < a.r;
+    if (b.c1 != a.c1) return b.c1 < a.c1;
+    return b.r < a.r2cls;
+}
+
+// --------------------------------------------- Step 2: non-sample order
+
+// Count sample-order entries that are mod-1 positions (R-index < n0).
+__global__ __launch_bounds__(kBlock) void k_ns_count(const int32_t *__restrict__ sa12, Dims d, uint32_t groups,
+                                                     uint32_t *__restrict__ counts) {
+    __shared__ uint32_t s_tmp[kBlock / kWave];
+    uint32_t t0, t1;
+    group_tiles(d.m, groups, blockIdx.x, &t0, &t1);
+    uint32_t c = 0;
+    for (uint32_t r = t0 * kScanTile + threadIdx.x; r < min(d.m, t1 * kScanTile); r += kBlock)
+        c += (uint32_t)sa12[r] < d.n0;
+    uint32_t tot;
+    dev::block_exclusive_sum(c, s_tmp, &tot);
+    if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+}
+
+// Emit mod-0 position 3*idx (predecessor of mod-1 entry idx) with key t_{3 idx}.
+template <typename CH>
+__global__ __launch_bounds__(kBlock) void k_ns_write(const CH *__restrict__ t, const int32_t *__restrict__ sa12,
+                                                     Dims d, uint32_t groups,
+                                                     const uint32_t *__restrict__ counts,
+                                                     uint32_t *__restrict__ keys0,
+                                                     uint32_t *__restrict__ vals0) {
+    __shared__ uint32_t s_tmp[kBlock / kWave];
+    uint32_t t0, t1;
+    group_tiles(d.m, groups, blockIdx.x, &t0, &t1);
+    uint32_t base = counts[blockIdx.x];
+    for (uint32_t tile = t0; tile < t1; ++tile) {
+        const uint32_t r0 = tile * kScanTile + threadIdx.x * kScanItems;
+        uint32_t idx[kScanItems];
+        uint32_t c = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint32_t r = r0 + i;
+            idx[i] = r < d.m ? (uint32_t)sa12[r] : 0xffffffffu;
+            c += idx[i] < d.n0;
+        }
+        uint32_t tot;
+        uint32_t j = base + dev::block_exclusive_sum(c, s_tmp, &tot);
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            if (idx[i] < d.n0) {
+                const uint32_t p = 3u * idx[i];
+                if (j < d.n0) {
+                    keys0[j] = sym(t, d.n, p);
+                    vals0[j] = p;
+                }
+                ++j;
+            }
+        }
+        base += tot;
+    }
+}
+
+// ------------------------------------------------------ Step 3: merge
+
+// A = mod-0 positions sorted (Step 2), B = sample order without the padding
+// position (R-indices). Merge path: the number of A elements among the first
+// `diag` outputs, by binary search.
+template <typename CH>
+__device__ __forceinline__ uint32_t merge_split(const Rec<CH> *rec, const uint32_t *A, uint32_t nA,
+                                                const int32_t *B, uint32_t nB, const Dims &d,
+                                                uint32_t diag) {
+    uint32_t lo = diag > nB ? diag - nB : 0u, hi = min(diag, nA);
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        const Key4 a = key_of<CH>(rec, min(A[mid], d.n - 1));
+        const Key4 b = key_of<CH>(rec, min(d.pos_of(min((uint32_t)B[diag - 1 - mid], d.m - 1)), d.n - 1));
+        if (!sample_less(b, a)) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+template <typename CH>
+__global__ __launch_bounds__(kBlock) void k_merge_partition(const Rec<CH> *__restrict__ rec,
+                                                            const uint32_t *__restrict__ A, uint32_t nA,
+                                                            const int32_t *__restrict__ B, uint32_t nB,
+                                                            Dims d, uint32_t parts,
+                                                            uint32_t *__restrict__ split) {
+    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    if (p > parts) return;
+    const uint64_t diag64 = (uint64_t)p * kMergeTile;
+    const uint32_t diag = (uint32_t)min<uint64_t>(diag64, (uint64_t)nA + nB);
+    split[p] = merge_split<CH>(rec, A, nA, B, nB, d, diag);
+}
+
+template <typename CH>
+__global__ __launch_bounds__(kBlock) void k_merge(const Rec<CH> *__restrict__ rec,
+                                                  const uint32_t *__restrict__ A, uint32_t nA,
+                                                  const int32_t *__restrict__ B, uint32_t nB, Dims d,
+                                                  const uint32_t *__restrict__ split,
+                                                  int32_t *__restrict__ sa) {
+    __shared__ Key4 s_key[kMergeTile];
+    __shared__ uint32_t s_pos[kMergeTile];
+    __shared__ int32_t s_out[kMergeTile];
+    const uint32_t total = nA + nB;
+    const uint32_t d0 = blockIdx.x * kMergeTile;
+    const uint32_t d1 = min(total, d0 + kMergeTile);
+    const uint32_t a0 = split[blockIdx.x], a1 = split[blockIdx.x + 1];
+    // A consistent comparator gives monotone splits; anything else stops the
+    // workgroup before it can index outside A or B (block-uniform exit).
+    if (a0 > a1 || a1 > nA || a0 > d0 || a1 > d1 || d0 - a0 > nB || d1 - a1 > nB || d1 - a1 < d0 - a0) return;
+    const uint32_t b0 = d0 - a0, b1 = d1 - a1;
+    const uint32_t na = a1 - a0, nb = b1 - b0, cnt = d1 - d0;
+    for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
+        uint32_t pos;
+        if (i < na) pos = A[a0 + i];
+        else pos = d.pos_of(min((uint32_t)B[b0 + (i - na)], d.m - 1));
+        pos = min(pos, d.n - 1);
+        s_pos[i] = pos;
+        s_key[i] = key_of<CH>(rec, pos);
+    }
+    __syncthreads();
+    const Key4 *sA = s_key;
+    const Key4 *sB = s_key + na;
+    const uint32_t diag = min(cnt, threadIdx.x * (uint32_t)kMergeItems);
+    const uint32_t dend = min(cnt, diag + (uint32_t)kMergeItems);
+    uint32_t lo = diag > nb ? diag - nb : 0u, hi = min(diag, na);
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (!sample_less(sB[diag - 1 - mid], sA[mid])) lo = mid + 1; else hi = mid;
+    }
+    uint32_t ia = lo, ib = diag - lo;
+    for (uint32_t o = diag; o < dend; ++o) {
+        bool take_a;
+        if (ia >= na) take_a = false;
+        else if (ib >= nb) take_a = true;
+        else take_a = !sample_less(sB[ib], sA[ia]);
+        if (take_a) { s_out[o] = (int32_t)s_pos[ia]; ++ia; }
+        else { s_out[o] = (int32_t)s_pos[na + ib]; ++ib; }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) sa[d0 + i] = s_out[i];
+}
+
+// ------------------------------------------------------------- driver
+
+struct HostHdr {
+    uint32_t error;
+    uint32_t maxname;
+};
+
+enum KeyMode { KM_U32, KM_U64, KM_STAGED };
+
+template <typename CH>
+lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Arena &ar, uint32_t *hdr,
+                     hipStream_t s, int depth) {
+    if (n == 0) return LOR_OK;
+    if (depth > 64) {
+        set_error("DC3 recursion deeper than 64 levels");
+        return LOR_EINVAL;
+    }
+    const bool run = !ar.measuring();
+    const Dims d = make_dims(n);
+    const int b = bits_for(alphabet);
+    const size_t mark_level = ar.mark();
+
+    int32_t *R;        // names of the sample triples; later rank12 (rank by R-index)
+    int32_t *sa12;     // sample order as R-indices
+    LOR_TAKE(ar, int32_t, d.m, R);
+    LOR_TAKE(ar, int32_t, d.m, sa12);
+    const size_t mark_tmp = ar.mark();
+
+    // ---- Step 1: sort the sample triples
+    KeyMode km = (3 * b <= 32) ? KM_U32 : (3 * b <= 64 ? KM_U64 : KM_STAGED);
+    if (!run) km = KM_U64;   // measuring: the largest footprint
+    uint32_t *counts;
+    LOR_TAKE(ar, uint32_t, radix_counts_words(d.m) + kMaxScanGroups + 64, counts);
+    uint32_t *gcount = counts + radix_counts_words(d.m);
+    uint32_t *tmpv;
+    LOR_TAKE(ar, uint32_t, d.m, tmpv);
+    const int per_sym = radix_passes(0, b);
+    const int passes = d.m <= 1 ? 0 : (km == KM_STAGED ? 3 * per_sym : radix_passes(0, 3 * b));
+    uint32_t *v0 = (passes % 2 == 0) ? (uint32_t *)sa12 : tmpv;
+    uint32_t *v1 = (passes % 2 == 0) ? tmpv : (uint32_t *)sa12;
+    const uint32_t g_el = grid_for(d.m);
+    uint32_t hmax = 0;
+
+    if (km == KM_U64) {
+        uint64_t *k0, *k1;
+        LOR_TAKE(ar, uint64_t, d.m, k0);
+        LOR_TAKE(ar, uint64_t, d.m, k1);
+        if (run) {
+            LOR_LAUNCH(F_KEYS, (double)d.m * 12 + (double)n * sizeof(CH), s,
+                       hipLaunchKernelGGL((k_sample_keys<CH, uint64_t>), dim3(g_el), dim3(kBlock), 0, s, t, d, b,
+                                          0, 0, k0, v0));
+            bool alt;
+            LOR_TRY(radix_sort<uint64_t>(k0, v0, k1, v1, d.m, 0, 3 * b, counts, s, &alt));
+            uint64_t *ks = alt ? k1 : k0;
+            if ((alt ? v1 : v0) != (uint32_t *)sa12) {
+                set_error("internal: sorted sample order not in its buffer");
+                return LOR_EINVAL;
+            }
+            const uint32_t G = scan_groups(d.m);
+            LOR_LAUNCH(F_NAME, (double)d.m * 8, s,
+                       hipLaunchKernelGGL((k_name_count<CH, uint64_t, false>), dim3(G), dim3(kBlock), 0, s, t, d,
+                                          ks, (const uint32_t *)sa12, G, gcount));
+            LOR_TRY(scan_block_totals(gcount, G, hdr + 1, s));
+            LOR_LAUNCH(F_NAME, (double)d.m * 16, s,
+                       hipLaunchKernelGGL((k_name_write<CH, uint64_t, false>), dim3(G), dim3(kBlock), 0, s, t, d,
+                                          ks, (const uint32_t *)sa12, G, gcount, R));
+        }
+    } else {
+        uint32_t *k0, *k1;
+        LOR_TAKE(ar, uint32_t, d.m, k0);
+        LOR_TAKE(ar, uint32_t, d.m, k1);
+        if (run) {
+            bool alt = false;
+            uint32_t *kc = k0, *ka = k1, *vc = v0, *va = v1;
+            auto swap_if = [&](bool a) {
+                if (a) { uint32_t *x = kc; kc = ka; ka = x; x = vc; vc = va; va = x; }
+            };
+            if (km == KM_U32) {
+                LOR_LAUNCH(F_KEYS, (double)d.m * 8 + (double)n * sizeof(CH), s,
+                           hipLaunchKernelGGL((k_sample_keys<CH, uint32_t>), dim3(g_el), dim3(kBlock), 0, s, t, d,
+                                              b, 0, 0, kc, vc));
+                LOR_TRY(radix_sort<uint32_t>(kc, vc, ka, va, d.m, 0, 3 * b, counts, s, &alt));
+                swap_if(alt);
+            } else {
+                // LSD over whole symbols: t_{i+2}, then t_{i+1}, then t_i.
+                LOR_LAUNCH(F_KEYS, (double)d.m * 8 + (double)d.m * sizeof(CH), s,
+                           hipLaunchKernelGGL((k_sample_keys<CH, uint32_t>), dim3(g_el), dim3(kBlock), 0, s, t, d,
+                                              b, 1, 2, kc, vc));
+                LOR_TRY(radix_sort<uint32_t>(kc, vc, ka, va, d.m, 0, b, counts, s, &alt));
+                swap_if(alt);
+                for (int delta = 1; delta >= 0; --delta) {
+                    LOR_LAUNCH(F_KEYS, (double)d.m * 8 + (double)d.m * sizeof(CH), s,
+                               hipLaunchKernelGGL((k_rekey<CH>), dim3(g_el), dim3(kBlock), 0, s, t, d, delta, vc, kc));
+                    LOR_TRY(radix_sort<uint32_t>(kc, vc, ka, va, d.m, 0, b, counts, s, &alt));
+                    swap_if(alt);
+                }
+            }
+            if (vc != (uint32_t *)sa12) {
+                set_error("internal: sorted sample order not in its buffer");
+                return LOR_EINVAL;
+            }
+            const uint32_t G = scan_groups(d.m);
+            if (km == KM_U32) {
+                LOR_LAUNCH(F_NAME, (double)d.m * 4, s,
+                           hipLaunchKernelGGL((k_name_count<CH, uint32_t, false>), dim3(G), dim3(kBlock), 0, s, t,
+                                              d, kc, vc, G, gcount));
+                LOR_TRY(scan_block_totals(gcount, G, hdr + 1, s));
+                LOR_LAUNCH(F_NAME, (double)d.m * 12, s,
+                           hipLaunchKernelGGL((k_name_write<CH, uint32_t, false>), dim3(G), dim3(kBlock), 0, s, t,
+                                              d, kc, vc, G, gcount, R));
+            } else {
+                LOR_LAUNCH(F_NAME, (double)d.m * 8, s,
+                           hipLaunchKernelGGL((k_name_count<CH, uint32_t, true>), dim3(G), dim3(kBlock), 0, s, t,
+                                              d, kc, vc, G, gcount));
+                LOR_TRY(scan_block_totals(gcount, G, hdr + 1, s));
+                LOR_LAUNCH(F_NAME, (double)d.m * 16, s,
+                           hipLaunchKernelGGL((k_name_write<CH, uint32_t, true>), dim3(G), dim3(kBlock), 0, s, t,
+                                              d, kc, vc, G, gcount, R));
+            }
+        }
+    }
+
+    bool unique = true;
+    if (run) {
+        HostHdr h;
+        LOR_HIP(hipMemcpyAsync(&h, hdr, sizeof(h), hipMemcpyDeviceToHost, s));
+        LOR_HIP(hipStreamSynchronize(s));
+        if (h.error) {
+            set_error("input base outside 0..3");
+            return LOR_EALPHABET;
+        }
+        hmax = h.maxname;
+        if (hmax > d.m || hmax == 0) {
+            set_error("internal: %u names for %u sample triples", hmax, d.m);
+            return LOR_EINVAL;
+        }
+        unique = (hmax == d.m);
+    } else {
+        unique = d.m < 2;
+        hmax = d.m;
+    }
+    ar.release(mark_tmp);
+
+    if (!unique) {
+        LOR_TRY(dc3_level<int32_t>(R, d.m, hmax, sa12, ar, hdr, s, depth + 1));
+        if (run)
+            LOR_LAUNCH(F_RANK, (double)d.m * 8, s,
+                       hipLaunchKernelGGL(k_rank_from_sa, dim3(g_el), dim3(kBlock), 0, s, sa12, d.m, R));
+    }
+    const int32_t *rank12 = R;
+
+    // ---- records for the merge
+    Rec<CH> *rec;
+    LOR_TAKE(ar, Rec<CH>, (size_t)d.n0 + 1, rec);
+    if (run)
+        LOR_LAUNCH(F_RECORDS, (double)(d.n0 + 1) * (sizeof(Rec<CH>) + 12) + (double)n * sizeof(CH), s,
+                   hipLaunchKernelGGL(k_records<CH>, dim3(grid_for(d.n0 + 1)), dim3(kBlock), 0, s, t, d, rank12,
+                                      rec));
+
+    // ---- Step 2: mod-0 suffixes
+    uint32_t *keys0, *vals0, *keys1, *vals1, *counts2;
+    LOR_TAKE(ar, uint32_t, d.n0, keys0);
+    LOR_TAKE(ar, uint32_t, d.n0, vals0);
+    LOR_TAKE(ar, uint32_t, d.n0, keys1);
+    LOR_TAKE(ar, uint32_t, d.n0, vals1);
+    LOR_TAKE(ar, uint32_t, radix_counts_words(d.n0) + kMaxScanGroups + 64, counts2);
+    uint32_t *gcount2 = counts2 + radix_counts_words(d.n0);
+    const uint32_t parts = div_up(n, kMergeTile);
+    uint32_t *split;
+    LOR_TAKE(ar, uint32_t, (size_t)parts + 1, split);
+    if (run) {
+        const uint32_t G = scan_groups(d.m);
+        LOR_LAUNCH(F_NONSAMPLE, (double)d.m * 4, s,
+                   hipLaunchKernelGGL(k_ns_count, dim3(G), dim3(kBlock), 0, s, sa12, d, G, gcount2));
+        LOR_TRY(scan_block_totals(gcount2, G, hdr + 2, s));
+        LOR_LAUNCH(F_NONSAMPLE, (double)d.m * 4 + (double)d.n0 * (8 + sizeof(CH)), s,
+                   hipLaunchKernelGGL(k_ns_write<CH>, dim3(G), dim3(kBlock), 0, s, t, sa12, d, G, gcount2, keys0,
+                                      vals0));
+        bool alt;
+        LOR_TRY(radix_sort<uint32_t>(keys0, vals0, keys1, vals1, d.n0, 0, b, counts2, s, &alt));
+        const uint32_t *A = alt ? vals1 : vals0;
+        const int32_t *B = sa12 + d.dummy;
+        const uint32_t nB = d.m - d.dummy;
+        LOR_LAUNCH(F_MERGE_PART, (double)(parts + 1) * 4, s,
+                   hipLaunchKernelGGL(k_merge_partition<CH>, dim3(div_up(parts + 1, kBlock)), dim3(kBlock), 0, s,
+                                      rec, A, d.n0, B, nB, d, parts, split));
+        LOR_LAUNCH(F_MERGE, (double)n * (4 + 4 + sizeof(Rec<CH>)), s,
+                   hipLaunchKernelGGL(k_merge<CH>, dim3(parts), dim3(kBlock), 0, s, rec, A, d.n0, B, nB, d, split,
+                                      sa));
+    }
+    ar.release(mark_level);
+    return LOR_OK;
+}
+
+}  // namespace
+
+lor_status dc3_u8(const uint8_t *text, uint32_t n, uint32_t alphabet, int32_t *sa, Arena &ar, uint32_t *hdr,
+                  hipStream_t s) {
+    return dc3_level<uint8_t>(text, n, alphabet, sa, ar, hdr, s, 0);
+}
+
+lor_status dc3_i32(const int32_t *text, uint32_t n, uint32_t alphabet, int32_t *sa, Arena &ar, uint32_t *hdr,
+                   hipStream_t s) {
+    return dc3_level<int32_t>(text, n, alphabet, sa, ar, hdr, s, 0);
+}
+
+size_t dc3_workspace_bound(uint64_t n) {
+    Arena ar;   // measuring
+    if (n == 0) return 0;
+    dc3_level<int32_t>(nullptr, (uint32_t)n, 0x7fffffffu, nullptr, ar, nullptr, nullptr, 0);
+    return ar.high + 4096;
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_words(uint32_t *p, uint32_t count) {
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < count; i += gridDim.x * kBlock) p[i] = 0;
+}
+
+lor_status zero_words(uint32_t *p, uint32_t count, hipStream_t s) {
+    if (!count) return LOR_OK;
+    LOR_LAUNCH(F_MISC, 4.0 * count, s,
+               hipLaunchKernelGGL(k_zero_words, dim3(grid_for(count)), dim3(kBlock), 0, s, p, count));
+    return LOR_OK;
+}
+
+lor_status join_text(const uint8_t *seqs, const int64_t *offsets, int32_t k, uint8_t *out, uint32_t *err_word,
+                     hipStream_t s) {
+    SeqStarts st;
+    st.k = k;
+    for (int j = 0; j <= k; ++j) st.start[j] = (int32_t)(offsets[j] + j);
+    const uint32_t N = (uint32_t)(offsets[k] + k);
+    if (N == 0) return LOR_OK;
+    LOR_LAUNCH(F_JOIN, 2.0 * N, s,
+               hipLaunchKernelGGL(k_join, dim3(grid_for(div_up(N, 4))), dim3(kBlock), 0, s, seqs, st, N, out,
+                                  err_word));
+    return LOR_OK;
+}
+
+}  // namespace lor

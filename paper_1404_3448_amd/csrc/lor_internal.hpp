@@ -1,0 +1,221 @@
+// Internal declarations shared by the liblor.so translation units:
+// error reporting, the workspace arena, kernel-family timing, and wave64
+// device primitives for gfx950.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lor.h"
+
+namespace lor {
+
+constexpr int kWave = 64;     // CDNA wavefront width
+constexpr int kBlock = 256;   // threads per workgroup for every kernel (4 waves)
+
+// ------------------------------------------------------------------ errors
+void set_error(const char *fmt, ...);
+
+#define LOR_TRY(expr)                        \
+    do {                                     \
+        lor_status st_ = (expr);             \
+        if (st_ != LOR_OK) return st_;       \
+    } while (0)
+
+#define LOR_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            ::lor::set_error("%s:%d: %s failed: %s", __FILE__, __LINE__, #call,          \
+                             hipGetErrorString(e_));                                    \
+            return LOR_EHIP;                                                            \
+        }                                                                               \
+    } while (0)
+
+#define LOR_CHECK_LAUNCH() LOR_HIP(hipGetLastError())
+
+// ------------------------------------------------------------------ arena
+// Bump allocator over the caller's workspace. With base == nullptr it only
+// measures (the size queries run the same carving code as the real calls).
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0;
+    size_t top = 0;
+    size_t high = 0;
+    bool overflow = false;
+
+    template <class T>
+    T *take(size_t count) {
+        size_t a = (top + 255) & ~size_t(255);
+        size_t need = a + count * sizeof(T);
+        if (base && need > cap) {
+            overflow = true;
+            return nullptr;
+        }
+        top = need;
+        if (top > high) high = top;
+        return base ? reinterpret_cast<T *>(base + a) : reinterpret_cast<T *>(uintptr_t(256));
+    }
+    size_t mark() const { return top; }
+    void release(size_t m) { top = m; }
+    bool measuring() const { return base == nullptr; }
+};
+
+#define LOR_TAKE(arena, T, count, ptr)                                                  \
+    do {                                                                                \
+        (ptr) = (arena).template take<T>(count);                                        \
+        if (!(ptr)) {                                                                   \
+            ::lor::set_error("workspace too small (%s:%d)", __FILE__, __LINE__);        \
+            return LOR_EWORKSPACE;                                                      \
+        }                                                                               \
+    } while (0)
+
+// Small device header at the start of every workspace: an error word and a
+// few result words read back by the host.
+struct WsHeader {
+    uint32_t error;        // bit 0: input base outside 0..3
+    uint32_t word[15];
+};
+constexpr size_t kHeaderBytes = 256;
+
+// Device count of compute units (queried once per device).
+int num_cus();
+
+// -------------------------------------------------------- kernel timing
+enum Family {
+    F_JOIN, F_KEYS, F_RADIX_COUNT, F_RADIX_SCAN, F_RADIX_SCATTER, F_NAME, F_RANK, F_RECORDS,
+    F_NONSAMPLE, F_MERGE_PART, F_MERGE, F_PHI, F_PLCP, F_PERMUTE, F_ST, F_QUERY, F_OVERLAP,
+    F_MISC, F_NUM
+};
+bool timing_on();
+int timing_begin(hipStream_t s, Family f, double bytes);
+void timing_end(int token, hipStream_t s);
+
+// Launch helper: records events around the launch when timing is enabled.
+#define LOR_LAUNCH(family, bytes, stream, ...)                                          \
+    do {                                                                                \
+        int tk_ = ::lor::timing_on() ? ::lor::timing_begin((stream), (family), (bytes)) : -1; \
+        __VA_ARGS__;                                                                    \
+        LOR_CHECK_LAUNCH();                                                             \
+        if (tk_ >= 0) ::lor::timing_end(tk_, (stream));                                 \
+    } while (0)
+
+inline uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+// Grid size for elementwise kernels: one thread per item, capped; kernels
+// stride over the rest.
+inline uint32_t grid_for(uint64_t items, uint32_t per_block = kBlock) {
+    uint64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 65536u * 8u) g = 65536u * 8u;
+    return (uint32_t)g;
+}
+
+inline int bits_for(uint64_t maxval) {   // bits needed to hold 0..maxval
+    int b = 0;
+    while (b < 64 && (maxval >> b) != 0) ++b;
+    return b;
+}
+
+// ------------------------------------------------------------ radix sort
+// Stable LSD sort of (key, u32 value) by key bits [bit_lo, bit_hi).
+// (k0, v0) hold the input; (k1, v1) are same-sized alternates. On return
+// *in_alt says whether the sorted data ended in (k1, v1).
+size_t radix_counts_words(uint64_t n);
+template <typename K>
+lor_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, uint32_t n, int bit_lo,
+                      int bit_hi, uint32_t *counts, hipStream_t s, bool *in_alt);
+int radix_passes(int bit_lo, int bit_hi);
+
+// ------------------------------------------------------------- device scan
+// Exclusive scan of `count` u32 block totals in place (one workgroup);
+// writes the grand total to *total.
+lor_status scan_block_totals(uint32_t *vals, uint32_t count, uint32_t *total, hipStream_t s);
+
+// ----------------------------------------------------------------- DC3
+// Suffix array of a text with symbols in 1..alphabet (u8 texts are read as
+// byte + 1). Carves its buffers from `ar`; with a measuring arena it only
+// records the worst-case footprint.
+lor_status dc3_u8(const uint8_t *text, uint32_t n, uint32_t alphabet, int32_t *sa, Arena &ar,
+                  uint32_t *hdr_dev, hipStream_t s);
+lor_status dc3_i32(const int32_t *text, uint32_t n, uint32_t alphabet, int32_t *sa, Arena &ar,
+                   uint32_t *hdr_dev, hipStream_t s);
+size_t dc3_workspace_bound(uint64_t n);
+
+// Zero `count` words on the stream with a kernel (no memset nodes).
+lor_status zero_words(uint32_t *p, uint32_t count, hipStream_t s);
+
+// Join: seqs + offsets -> joined text (separator 4+j after sequence j);
+// sets bit 0 of *err_word on a base outside 0..3.
+lor_status join_text(const uint8_t *seqs, const int64_t *offsets, int32_t k, uint8_t *out,
+                     uint32_t *err_word, hipStream_t s);
+
+// ------------------------------------------------------------------ LCP
+size_t lcp_workspace(uint64_t n);
+lor_status lcp_build(const uint8_t *text, uint32_t n, const int32_t *sa, int32_t *lcp, int32_t *isa,
+                     Arena &ar, hipStream_t s);
+
+// ------------------------------------------------------------------ RMQ
+uint64_t rmq_level_offset(uint64_t n, int level);   // entries before `level` (levels from 1)
+lor_status rmq_build_levels(const int32_t *lcp, uint32_t n, int32_t *table, int levels, hipStream_t s);
+lor_status rmq_queries(const int32_t *table, uint32_t n, int levels, const int32_t *lcp,
+                       const int32_t *isa, int mode, const int32_t *qi, const int32_t *qj,
+                       uint32_t nq, int32_t *min_out, int32_t *argmin_out, hipStream_t s);
+
+// -------------------------------------------------------------- overlap
+constexpr int kMaxSeqs = 251;   // separators 4..254, so byte + 1 fits a byte
+struct SeqStarts {           // joined start of every sequence, plus N
+    int32_t start[kMaxSeqs + 1];
+    int32_t k;
+};
+size_t overlap_workspace(uint64_t n);
+lor_status overlap_scan(const int32_t *sa, const int32_t *lcp, uint32_t n, const SeqStarts &st,
+                        Arena &ar, hipStream_t s, int64_t result[5]);
+
+}  // namespace lor
+
+// ------------------------------------------------------- device helpers
+namespace lor {
+namespace dev {
+
+__device__ __forceinline__ unsigned lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// Number of set bits of m in lanes below the calling lane.
+__device__ __forceinline__ unsigned count_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x) {
+    const unsigned lane = threadIdx.x & 63u;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= (unsigned)o) x += y;
+    }
+    return x;
+}
+
+// Exclusive sum over the 256 threads of the block. tmp: 4 words of LDS.
+// Contains barriers; every thread of the block must call it.
+__device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t *tmp, uint32_t *total) {
+    const unsigned lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    uint32_t inc = wave_inclusive_sum(v);
+    if (lane == 63) tmp[w] = inc;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i) {
+        uint32_t t = tmp[i];
+        base += (i < (int)w) ? t : 0u;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - v;
+}
+
+}  // namespace dev
+}  // namespace lor

@@ -1,0 +1,237 @@
+// Longest overlap region on gfx950 (Section III problem statement: the
+// longest common prefix of suffixes of different sequences, with its
+// positions).
+//
+// Pass 1 (max): L = largest LCP[r] over ranks whose two suffixes start in
+//   different sequences; a per-thread chunk scan, a workgroup reduction and
+//   one atomicMax per workgroup (max is order-independent, so deterministic).
+// Pass 2 (positions): the suffixes sharing one L-symbol prefix form a maximal
+//   run of ranks whose LCP is >= L. The reported pair is the lexicographically
+//   smallest (p, q), p < q, from different sequences inside one run; in a run
+//   p is its smallest position and q the smallest position of another
+//   sequence. Runs are summarised by (m1, s1, m2, s2): the smallest position
+//   and its sequence, and the smallest position whose sequence differs from
+//   s1. Merging two summaries keeps this exact, so chunks of ranks are
+//   summarised independently (head = part of a run begun earlier, tail =
+//   last open run, best = best pair of the runs closed inside) and combined
+//   in rank order by an associative rule: a workgroup tree, then one
+//   workgroup over the workgroup results.
+#include <climits>
+
+#include "lor_internal.hpp"
+
+namespace lor {
+
+namespace {
+
+constexpr uint32_t kChunk = 32;                       // ranks per thread
+constexpr uint32_t kGroupRanks = kChunk * kBlock;
+
+struct RunSum {
+    int32_t m1, s1, m2, s2;
+};
+struct ChunkSum {
+    RunSum head, tail;
+    int32_t has_b, bp, bq, pad;
+};
+
+__device__ __forceinline__ RunSum run_empty() { return RunSum{INT_MAX, -1, INT_MAX, -1}; }
+
+__device__ __forceinline__ RunSum run_merge(const RunSum &x, const RunSum &y) {
+    const bool xf = x.m1 <= y.m1;
+    const RunSum &f = xf ? x : y;
+    const RunSum &o = xf ? y : x;
+    RunSum r{f.m1, f.s1, f.m2, f.s2};
+    if (o.m1 != INT_MAX && o.s1 != f.s1 && o.m1 < r.m2) { r.m2 = o.m1; r.s2 = o.s1; }
+    if (o.m2 != INT_MAX && o.s2 != f.s1 && o.m2 < r.m2) { r.m2 = o.m2; r.s2 = o.s2; }
+    return r;
+}
+
+__device__ __forceinline__ void best_update(int32_t &bp, int32_t &bq, int32_t p, int32_t q) {
+    if (p < bp || (p == bp && q < bq)) { bp = p; bq = q; }
+}
+
+__device__ __forceinline__ void finalize(const RunSum &r, int32_t &bp, int32_t &bq) {
+    if (r.m1 != INT_MAX && r.m2 != INT_MAX) best_update(bp, bq, r.m1, r.m2);
+}
+
+__device__ __forceinline__ ChunkSum chunk_empty() {
+    ChunkSum c;
+    c.head = run_empty();
+    c.tail = run_empty();
+    c.has_b = 0;
+    c.bp = INT_MAX;
+    c.bq = INT_MAX;
+    c.pad = 0;
+    return c;
+}
+
+// x precedes y in rank order.
+__device__ __forceinline__ ChunkSum chunk_combine(const ChunkSum &x, const ChunkSum &y) {
+    ChunkSum r;
+    r.pad = 0;
+    if (!x.has_b) {
+        r.head = run_merge(x.head, y.head);
+        r.has_b = y.has_b;
+        r.tail = y.tail;
+        r.bp = y.bp;
+        r.bq = y.bq;
+    } else {
+        r.head = x.head;
+        r.has_b = 1;
+        r.bp = x.bp;
+        r.bq = x.bq;
+        if (y.has_b) {
+            finalize(run_merge(x.tail, y.head), r.bp, r.bq);
+            best_update(r.bp, r.bq, y.bp, y.bq);
+            r.tail = y.tail;
+        } else {
+            r.tail = run_merge(x.tail, y.head);
+        }
+    }
+    return r;
+}
+
+__device__ __forceinline__ int32_t seq_of(const int32_t *s_start, int k, int32_t p) {
+    int lo = 0, hi = k - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_start[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_init(uint32_t *w, int count) {
+    if (threadIdx.x < (unsigned)count) w[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cross_max(const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp,
+                                                      uint32_t n, SeqStarts st, uint32_t *__restrict__ out_max) {
+    __shared__ int32_t s_start[kMaxSeqs + 1];
+    __shared__ int32_t s_red[kBlock / kWave];
+    for (int i = threadIdx.x; i <= st.k; i += kBlock) s_start[i] = st.start[i];
+    __syncthreads();
+    int32_t best = 0;
+    const uint32_t chunks = (n + kChunk - 1) / kChunk;
+    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < chunks; c += gridDim.x * kBlock) {
+        const uint32_t r0 = c * kChunk, r1 = min(n, r0 + kChunk);
+        int32_t prev = r0 ? seq_of(s_start, st.k, sa[r0 - 1]) : -1;
+        for (uint32_t r = r0; r < r1; ++r) {
+            const int32_t cur = seq_of(s_start, st.k, sa[r]);
+            if (r > 0 && cur != prev) best = max(best, lcp[r]);
+            prev = cur;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o, 64));
+    if ((threadIdx.x & 63u) == 0) s_red[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t b = s_red[0];
+        for (int i = 1; i < kBlock / kWave; ++i) b = max(b, s_red[i]);
+        if (b > 0) atomicMax(out_max, (uint32_t)b);
+    }
+}
+
+__device__ void block_reduce_chunks(ChunkSum *s, ChunkSum mine) {
+    s[threadIdx.x] = mine;
+    __syncthreads();
+    for (unsigned stride = 1; stride < kBlock; stride <<= 1) {
+        if ((threadIdx.x & (2 * stride - 1)) == 0) s[threadIdx.x] = chunk_combine(s[threadIdx.x], s[threadIdx.x + stride]);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_runs(const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp,
+                                                 uint32_t n, SeqStarts st, const uint32_t *__restrict__ Lp,
+                                                 ChunkSum *__restrict__ out) {
+    __shared__ int32_t s_start[kMaxSeqs + 1];
+    __shared__ ChunkSum s_sum[kBlock];
+    for (int i = threadIdx.x; i <= st.k; i += kBlock) s_start[i] = st.start[i];
+    __syncthreads();
+    const int32_t L = (int32_t)*Lp;
+    const uint32_t r0 = blockIdx.x * kGroupRanks + threadIdx.x * kChunk;
+    const uint32_t r1 = min(n, r0 + kChunk);
+    ChunkSum c = chunk_empty();
+    for (uint32_t r = r0; r < r1; ++r) {
+        const int32_t p = sa[r];
+        const RunSum e{p, seq_of(s_start, st.k, p), INT_MAX, -1};
+        if (r == 0 || lcp[r] < L) {           // r starts a run
+            if (c.has_b) finalize(c.tail, c.bp, c.bq);
+            c.has_b = 1;
+            c.tail = e;
+        } else if (c.has_b) {
+            c.tail = run_merge(c.tail, e);
+        } else {
+            c.head = run_merge(c.head, e);
+        }
+    }
+    block_reduce_chunks(s_sum, c);
+    if (threadIdx.x == 0) out[blockIdx.x] = s_sum[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_runs_final(const ChunkSum *__restrict__ in, uint32_t count,
+                                                       uint32_t *__restrict__ result) {
+    __shared__ ChunkSum s_sum[kBlock];
+    const uint32_t per = (count + kBlock - 1) / kBlock;
+    const uint32_t b = min(count, threadIdx.x * per), e = min(count, b + per);
+    ChunkSum c = chunk_empty();
+    for (uint32_t i = b; i < e; ++i) c = chunk_combine(c, in[i]);
+    block_reduce_chunks(s_sum, c);
+    if (threadIdx.x == 0) {
+        ChunkSum g = s_sum[0];
+        int32_t bp = g.bp, bq = g.bq;
+        if (g.has_b) finalize(g.tail, bp, bq);
+        result[0] = (uint32_t)bp;
+        result[1] = (uint32_t)bq;
+    }
+}
+
+}  // namespace
+
+size_t overlap_workspace(uint64_t n) {
+    return ((n + kGroupRanks - 1) / kGroupRanks + 1) * sizeof(ChunkSum) + 1024;
+}
+
+lor_status overlap_scan(const int32_t *sa, const int32_t *lcp, uint32_t n, const SeqStarts &st, Arena &ar,
+                        hipStream_t s, int64_t result[5]) {
+    uint32_t *words;
+    LOR_TAKE(ar, uint32_t, 64, words);
+    const uint32_t groups = div_up(n, kGroupRanks);
+    ChunkSum *sums;
+    LOR_TAKE(ar, ChunkSum, (size_t)groups + 1, sums);
+    for (int x = 0; x < 5; ++x) result[x] = -1;
+    result[0] = 0;
+    if (n < 2) return LOR_OK;
+    LOR_LAUNCH(F_MISC, 0, s, hipLaunchKernelGGL(k_init, dim3(1), dim3(kBlock), 0, s, words, 4));
+    const uint32_t chunks = div_up(n, kChunk);
+    LOR_LAUNCH(F_OVERLAP, (double)n * 8, s,
+               hipLaunchKernelGGL(k_cross_max, dim3(grid_for(chunks)), dim3(kBlock), 0, s, sa, lcp, n, st, words));
+    uint32_t L = 0;
+    LOR_HIP(hipMemcpyAsync(&L, words, 4, hipMemcpyDeviceToHost, s));
+    LOR_HIP(hipStreamSynchronize(s));
+    if (L == 0) return LOR_OK;
+    LOR_LAUNCH(F_OVERLAP, (double)n * 8, s,
+               hipLaunchKernelGGL(k_runs, dim3(groups), dim3(kBlock), 0, s, sa, lcp, n, st, words, sums));
+    LOR_LAUNCH(F_OVERLAP, (double)groups * sizeof(ChunkSum), s,
+               hipLaunchKernelGGL(k_runs_final, dim3(1), dim3(kBlock), 0, s, sums, groups, words + 1));
+    uint32_t pq[2];
+    LOR_HIP(hipMemcpyAsync(pq, words + 1, 8, hipMemcpyDeviceToHost, s));
+    LOR_HIP(hipStreamSynchronize(s));
+    const int32_t p = (int32_t)pq[0], q = (int32_t)pq[1];
+    if (p == INT_MAX || q == INT_MAX || p < 0 || q < 0) {
+        set_error("internal: no position pair for overlap length %u", L);
+        return LOR_EINVAL;
+    }
+    auto locate = [&](int32_t pos, int64_t *seq, int64_t *off) {
+        int j = 0;
+        while (j + 1 < st.k && st.start[j + 1] <= pos) ++j;
+        *seq = j;
+        *off = pos - st.start[j];
+    };
+    result[0] = L;
+    locate(p, &result[1], &result[2]);
+    locate(q, &result[3], &result[4]);
+    return LOR_OK;
+}
+
+}  // namespace lor

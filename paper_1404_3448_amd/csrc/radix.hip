@@ -1,0 +1,248 @@
+// Stable LSD radix sort of (key, u32 value) pairs on gfx950.
+//
+// Section IV sorts DC3's sample and non-sample keys with a radix sort that
+// walks the digits from least to most significant, each pass a stable split
+// computed with a prefix scan (one bit per pass in the paper's kernel).
+// Here a pass handles an 8-bit digit and runs as three kernels:
+//   1. count  : every workgroup owns a contiguous run of tiles and builds the
+//               digit histogram of its run in LDS (per-wave sub-histograms);
+//   2. scan   : one workgroup turns the digit-major table counts[d][g] into
+//               exclusive global offsets;
+//   3. scatter: every workgroup walks its tiles in order; inside a tile each
+//               wave ranks its elements by digit with 8 ballots per round
+//               (lanes with the same digit form a peer mask; the rank is the
+//               number of peers in lower lanes), the tile is reordered by
+//               digit in LDS, and written out so that runs of equal digits
+//               leave as contiguous stores.
+// Element order inside a tile is wave-major then round-major then lane, so
+// ranks follow input order and every pass is stable.
+#include "lor_internal.hpp"
+
+namespace lor {
+
+namespace {
+
+constexpr int kDigitBits = 8;
+constexpr int kBins = 1 << kDigitBits;
+constexpr uint32_t kMaxGroups = 1024;     // workgroups per pass (fixed: workspace sizes are device-independent)
+
+template <typename K> struct RadixCfg;
+template <> struct RadixCfg<uint32_t> { static constexpr int kItems = 16; };
+template <> struct RadixCfg<uint64_t> { static constexpr int kItems = 8; };
+
+__device__ __forceinline__ void tile_range(uint32_t tiles, uint32_t groups, uint32_t g, uint32_t *t0,
+                                           uint32_t *t1) {
+    *t0 = (uint32_t)((uint64_t)tiles * g / groups);
+    *t1 = (uint32_t)((uint64_t)tiles * (g + 1) / groups);
+}
+
+template <typename K, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_radix_count(const K *__restrict__ keys, uint32_t n,
+                                                        uint32_t tiles, uint32_t groups, int shift,
+                                                        uint32_t mask, uint32_t *__restrict__ counts) {
+    constexpr uint32_t TILE = kBlock * ITEMS;
+    __shared__ uint32_t hist[kBlock / kWave][kBins];
+    const unsigned tid = threadIdx.x, w = tid >> 6;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i) hist[i][tid] = 0;
+    __syncthreads();
+    uint32_t t0, t1;
+    tile_range(tiles, groups, blockIdx.x, &t0, &t1);
+    for (uint32_t t = t0; t < t1; ++t) {
+        const uint32_t base = t * TILE + tid;
+        K k[ITEMS];
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            uint32_t e = base + r * kBlock;
+            k[r] = (e < n) ? keys[e] : K(0);
+        }
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            uint32_t e = base + r * kBlock;
+            if (e < n) atomicAdd(&hist[w][(uint32_t)(k[r] >> shift) & mask], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i) s += hist[i][tid];
+    counts[(size_t)tid * groups + blockIdx.x] = s;
+}
+
+template <typename K, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const K *__restrict__ kin,
+                                                          const uint32_t *__restrict__ vin,
+                                                          K *__restrict__ kout,
+                                                          uint32_t *__restrict__ vout, uint32_t n,
+                                                          uint32_t tiles, uint32_t groups, int shift,
+                                                          int nbits,
+                                                          const uint32_t *__restrict__ offs) {
+    constexpr uint32_t TILE = kBlock * ITEMS;
+    constexpr int W = kBlock / kWave;
+    __shared__ uint32_t s_cnt[W][kBins];   // per-wave digit counters, then digit bases per wave
+    __shared__ uint32_t s_base[kBins];     // global output base of every digit for this group
+    __shared__ uint32_t s_start[kBins];    // first tile-local slot of every digit
+    __shared__ uint32_t s_tmp[W];
+    __shared__ K s_key[TILE];
+    __shared__ uint32_t s_val[TILE];
+
+    const unsigned tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+    const uint32_t mask = (1u << nbits) - 1u;
+    s_base[tid] = offs[(size_t)tid * groups + blockIdx.x];
+    uint32_t t0, t1;
+    tile_range(tiles, groups, blockIdx.x, &t0, &t1);
+
+    for (uint32_t t = t0; t < t1; ++t) {
+        const uint32_t base = t * TILE;
+        const uint32_t nvalid = min(TILE, n - base);
+#pragma unroll
+        for (int i = 0; i < W; ++i) s_cnt[i][tid] = 0;
+        __syncthreads();
+
+        const uint32_t wfirst = base + w * (kWave * ITEMS) + lane;
+        K k[ITEMS];
+        uint32_t v[ITEMS];
+        uint32_t rk[ITEMS];
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            uint32_t e = wfirst + r * kWave;
+            bool ok = e < n;
+            k[r] = ok ? kin[e] : K(0);
+            v[r] = ok ? vin[e] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const bool ok = (wfirst + r * kWave) < n;
+            const uint32_t d = (uint32_t)(k[r] >> shift) & mask;
+            uint64_t peers = __ballot(ok);
+            for (int b = 0; b < nbits; ++b) {
+                const bool set = (d >> b) & 1u;
+                const uint64_t m = __ballot(set);
+                peers &= set ? m : ~m;
+            }
+            const uint32_t below = dev::count_below(peers);
+            uint32_t old = 0;
+            if (ok) old = s_cnt[w][d];
+            // All lanes of the wave read before the lowest peer writes: LDS
+            // accesses of one wave execute in program order.
+            if (ok && below == 0) s_cnt[w][d] = old + (uint32_t)__popcll(peers);
+            rk[r] = old + below;
+        }
+        __syncthreads();
+
+        const uint32_t c0 = s_cnt[0][tid], c1 = s_cnt[1][tid], c2 = s_cnt[2][tid], c3 = s_cnt[3][tid];
+        const uint32_t tot = c0 + c1 + c2 + c3;
+        uint32_t all;
+        const uint32_t start = dev::block_exclusive_sum(tot, s_tmp, &all);
+        s_cnt[0][tid] = start;
+        s_cnt[1][tid] = start + c0;
+        s_cnt[2][tid] = start + c0 + c1;
+        s_cnt[3][tid] = start + c0 + c1 + c2;
+        s_start[tid] = start;
+        __syncthreads();
+
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            if ((wfirst + r * kWave) < n) {
+                const uint32_t d = (uint32_t)(k[r] >> shift) & mask;
+                const uint32_t lp = s_cnt[w][d] + rk[r];
+                s_key[lp] = k[r];
+                s_val[lp] = v[r];
+            }
+        }
+        __syncthreads();
+
+        for (uint32_t i = tid; i < nvalid; i += kBlock) {
+            const K key = s_key[i];
+            const uint32_t d = (uint32_t)(key >> shift) & mask;
+            const uint32_t g = s_base[d] + (i - s_start[d]);
+            kout[g] = key;
+            vout[g] = s_val[i];
+        }
+        __syncthreads();
+        s_base[tid] += tot;
+    }
+}
+
+// Exclusive scan of `count` words in place by one 1024-thread workgroup;
+// each thread owns a contiguous slice.
+__global__ __launch_bounds__(1024) void k_scan_inplace(uint32_t *__restrict__ vals, uint32_t count,
+                                                       uint32_t *__restrict__ total) {
+    __shared__ uint32_t s_w[16];
+    const unsigned tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+    const uint32_t per = (count + 1023u) / 1024u;
+    const uint32_t b = min(count, tid * per), e = min(count, b + per);
+    uint32_t s = 0;
+    for (uint32_t i = b; i < e; ++i) s += vals[i];
+    uint32_t inc = dev::wave_inclusive_sum(s);
+    if (lane == 63) s_w[w] = inc;
+    __syncthreads();
+    uint32_t wb = 0, tot = 0;
+    for (int i = 0; i < 16; ++i) {
+        uint32_t x = s_w[i];
+        wb += (i < (int)w) ? x : 0u;
+        tot += x;
+    }
+    uint32_t run = wb + inc - s;
+    for (uint32_t i = b; i < e; ++i) {
+        uint32_t x = vals[i];
+        vals[i] = run;
+        run += x;
+    }
+    if (tid == 0 && total) *total = tot;
+}
+
+template <typename K>
+uint32_t groups_for(uint32_t n, uint32_t *tiles) {
+    constexpr uint32_t TILE = kBlock * RadixCfg<K>::kItems;
+    *tiles = div_up(n, TILE);
+    return *tiles < kMaxGroups ? (*tiles ? *tiles : 1) : kMaxGroups;
+}
+
+}  // namespace
+
+size_t radix_counts_words(uint64_t) { return (size_t)kBins * kMaxGroups + 64; }
+
+int radix_passes(int bit_lo, int bit_hi) {
+    return bit_hi > bit_lo ? (bit_hi - bit_lo + kDigitBits - 1) / kDigitBits : 0;
+}
+
+lor_status scan_block_totals(uint32_t *vals, uint32_t count, uint32_t *total, hipStream_t s) {
+    LOR_LAUNCH(F_RADIX_SCAN, 8.0 * count, s,
+               hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, vals, count, total));
+    return LOR_OK;
+}
+
+template <typename K>
+lor_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, uint32_t n, int bit_lo, int bit_hi,
+                      uint32_t *counts, hipStream_t s, bool *in_alt) {
+    constexpr int ITEMS = RadixCfg<K>::kItems;
+    *in_alt = false;
+    if (n <= 1 || bit_hi <= bit_lo) return LOR_OK;
+    uint32_t tiles;
+    const uint32_t groups = groups_for<K>(n, &tiles);
+    K *ki = k0, *ko = k1;
+    uint32_t *vi = v0, *vo = v1;
+    for (int shift = bit_lo; shift < bit_hi; shift += kDigitBits) {
+        const int nbits = min(kDigitBits, bit_hi - shift);
+        const uint32_t mask = (1u << nbits) - 1u;
+        LOR_LAUNCH(F_RADIX_COUNT, (double)n * sizeof(K), s,
+                   hipLaunchKernelGGL((k_radix_count<K, ITEMS>), dim3(groups), dim3(kBlock), 0, s, ki, n,
+                                      tiles, groups, shift, mask, counts));
+        LOR_TRY(scan_block_totals(counts, (uint32_t)kBins * groups, nullptr, s));
+        LOR_LAUNCH(F_RADIX_SCATTER, (double)n * 2.0 * (sizeof(K) + 4), s,
+                   hipLaunchKernelGGL((k_radix_scatter<K, ITEMS>), dim3(groups), dim3(kBlock), 0, s, ki,
+                                      vi, ko, vo, n, tiles, groups, shift, nbits, counts));
+        K *tk = ki; ki = ko; ko = tk;
+        uint32_t *tv = vi; vi = vo; vo = tv;
+        *in_alt = !*in_alt;
+    }
+    return LOR_OK;
+}
+
+template lor_status radix_sort<uint32_t>(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, int, int,
+                                         uint32_t *, hipStream_t, bool *);
+template lor_status radix_sort<uint64_t>(uint64_t *, uint32_t *, uint64_t *, uint32_t *, uint32_t, int, int,
+                                         uint32_t *, hipStream_t, bool *);
+
+}  // namespace lor

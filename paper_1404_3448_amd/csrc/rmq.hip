@@ -1,0 +1,114 @@
+// Range minimum over the LCP array on gfx950 (Section III: the lcp of two
+// suffixes is the minimum LCP between their ranks; RMQ returns the position
+// of a smallest element in a range).
+//
+// The paper answers RMQ through a Cartesian tree, an Euler tour and +-1RMQ.
+// Here the structure is a sparse table: level k holds the minimum of every
+// window of 2^k LCP entries, built level by level from level k-1 (two reads,
+// one write per entry, all streaming), and a query reads two overlapping
+// windows that cover its range. With 288 GB of HBM the table fits next to
+// the 1G-suffix arrays, and every query costs four independent gathers
+// (two ISA entries, two table entries) instead of a pointer walk.
+#include "lor_internal.hpp"
+
+namespace lor {
+
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_st_level(const int32_t *__restrict__ prev, uint32_t half,
+                                                     uint32_t cnt, int32_t *__restrict__ cur) {
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock)
+        cur[i] = min(prev[i], prev[i + half]);
+}
+
+struct Levels {
+    const int32_t *lcp;
+    const int32_t *table;
+    uint32_t n;
+    int levels;
+};
+
+__device__ __forceinline__ uint64_t level_offset_dev(uint64_t n, int level) {
+    // entries of levels 1..level-1: sum over k of (n - 2^k + 1)
+    const uint64_t k = (uint64_t)level - 1;
+    return k * (n + 1) - ((2ull << k) - 2ull);
+}
+
+__device__ __forceinline__ const int32_t *level_ptr(const Levels &L, int k) {
+    return k == 0 ? L.lcp : L.table + level_offset_dev(L.n, k);
+}
+
+// min of a[lo..hi] (lo <= hi) and, when want_pos, its leftmost position.
+__device__ __forceinline__ int32_t range_min(const Levels &L, uint32_t lo, uint32_t hi, bool want_pos,
+                                             int32_t *pos) {
+    const uint32_t len = hi - lo + 1;
+    const int k = 31 - __builtin_clz(len);
+    const int32_t *lv = level_ptr(L, k);
+    const int32_t v = min(lv[lo], lv[hi + 1 - (1u << k)]);
+    if (want_pos) {
+        uint32_t p = lo;
+        for (int kk = k; kk >= 0; --kk) {
+            const uint32_t w = 1u << kk;
+            if (p + w - 1 <= hi && level_ptr(L, kk)[p] > v) p += w;
+        }
+        *pos = (int32_t)p;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_query(Levels L, const int32_t *__restrict__ isa, int mode,
+                                                  const int32_t *__restrict__ qi, const int32_t *__restrict__ qj,
+                                                  uint32_t nq, int32_t *__restrict__ out_min,
+                                                  int32_t *__restrict__ out_arg) {
+    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < nq; q += gridDim.x * kBlock) {
+        const int32_t a = qi[q], b = qj[q];
+        int32_t v = -1, pos = -1;
+        if (mode == 0) {
+            if (a >= 0 && b >= a && (uint32_t)b < L.n) v = range_min(L, (uint32_t)a, (uint32_t)b, out_arg != nullptr, &pos);
+        } else if (a >= 0 && b >= 0 && (uint32_t)a < L.n && (uint32_t)b < L.n) {
+            if (a == b) {
+                v = (int32_t)(L.n - (uint32_t)a);
+            } else {
+                const int32_t ra = isa[a], rb = isa[b];
+                if (ra != rb && (uint32_t)ra < L.n && (uint32_t)rb < L.n) {
+                    const uint32_t lo = (uint32_t)min(ra, rb) + 1u, hi = (uint32_t)max(ra, rb);
+                    v = range_min(L, lo, hi, out_arg != nullptr, &pos);
+                }
+            }
+        }
+        out_min[q] = v;
+        if (out_arg) out_arg[q] = pos;
+    }
+}
+
+}  // namespace
+
+uint64_t rmq_level_offset(uint64_t n, int level) {
+    const uint64_t k = (uint64_t)level - 1;
+    return k * (n + 1) - ((2ull << k) - 2ull);
+}
+
+lor_status rmq_build_levels(const int32_t *lcp, uint32_t n, int32_t *table, int levels, hipStream_t s) {
+    for (int k = 1; k <= levels; ++k) {
+        const int32_t *prev = k == 1 ? lcp : table + rmq_level_offset(n, k - 1);
+        int32_t *cur = table + rmq_level_offset(n, k);
+        const uint32_t half = 1u << (k - 1);
+        const uint32_t cnt = n - (1u << k) + 1u;
+        LOR_LAUNCH(F_ST, (double)cnt * 8, s,
+                   hipLaunchKernelGGL(k_st_level, dim3(grid_for(cnt)), dim3(kBlock), 0, s, prev, half, cnt, cur));
+    }
+    return LOR_OK;
+}
+
+lor_status rmq_queries(const int32_t *table, uint32_t n, int levels, const int32_t *lcp, const int32_t *isa,
+                       int mode, const int32_t *qi, const int32_t *qj, uint32_t nq, int32_t *min_out,
+                       int32_t *argmin_out, hipStream_t s) {
+    if (nq == 0) return LOR_OK;
+    Levels L{lcp, table, n, levels};
+    LOR_LAUNCH(F_QUERY, (double)nq * (mode ? 28 : 20), s,
+               hipLaunchKernelGGL(k_query, dim3(grid_for(nq)), dim3(kBlock), 0, s, L, isa, mode, qi, qj, nq,
+                                  min_out, argmin_out));
+    return LOR_OK;
+}
+
+}  // namespace lor

@@ -1,0 +1,348 @@
+"""Python binding of liblor.so (ctypes). Argument marshalling only.
+
+Every function has the name of the C entry point it calls and runs that
+entry point on torch's current HIP stream (or the stream passed in). Device
+buffers are torch tensors on a ROCm device; the library itself never
+allocates device memory, so workspaces and outputs are allocated here with
+torch when the caller does not pass them. There is no fallback: if the built
+library is missing, loading raises.
+
+Unsigned 32-bit keys travel in torch.int32 tensors and 64-bit keys in
+torch.int64 tensors (same bits).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblor.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "lor.h")
+
+LOR_OK, LOR_EINVAL, LOR_EALPHABET, LOR_ETOOLARGE, LOR_EWORKSPACE, LOR_EHIP, LOR_ESTALE = range(7)
+
+_lib = None
+
+
+class LorError(RuntimeError):
+    def __init__(self, fn: str, status: int, detail: str):
+        self.status = status
+        self.detail = detail
+        super().__init__(f"{fn}: status {status} ({_status_string(status)}): {detail}")
+
+
+class lor_rmq(ctypes.Structure):
+    _fields_ = [("table", ctypes.c_void_p), ("n", ctypes.c_int64), ("levels", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class lor_overlap(ctypes.Structure):
+    _fields_ = [("length", ctypes.c_int64), ("seq_p", ctypes.c_int32), ("seq_q", ctypes.c_int32),
+                ("off_p", ctypes.c_int64), ("off_q", ctypes.c_int64)]
+
+
+class lor_timing(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+def header_functions() -> list:
+    """Names of the functions include/lor.h declares."""
+    with open(HEADER_PATH) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lor_[a-z0-9_]+)\s*\(", text)))
+
+
+def lib():
+    """Load liblor.so (after torch, so both use the same HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (loads the HIP runtime liblor.so links against)
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                           "(python -m paper_1404_3448_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    sig = {
+        "lor_status_string": ([I32], ctypes.c_char_p),
+        "lor_last_error": ([], ctypes.c_char_p),
+        "lor_version": ([], I32),
+        "lor_build_sa_workspace": ([I64, I32], SZ),
+        "lor_build_sa": ([P, P, I32, P, P, P, SZ, P], I32),
+        "lor_suffix_array_workspace": ([I64], SZ),
+        "lor_suffix_array_i32": ([P, I64, I32, P, P, SZ, P], I32),
+        "lor_build_lcp_workspace": ([I64], SZ),
+        "lor_build_lcp": ([P, I64, P, P, P, P, SZ, P], I32),
+        "lor_rmq_bytes": ([I64], SZ),
+        "lor_rmq_build": ([P, I64, P, SZ, ctypes.POINTER(lor_rmq), P], I32),
+        "lor_rmq_query": ([ctypes.POINTER(lor_rmq), P, P, I32, P, P, I64, P, P, P], I32),
+        "lor_longest_overlap_workspace": ([I64, I32], SZ),
+        "lor_longest_overlap": ([P, P, I64, P, I32, ctypes.POINTER(lor_overlap), P, SZ, P], I32),
+        "lor_sort_pairs_workspace": ([I64, I32], SZ),
+        "lor_sort_pairs_u32": ([P, P, I64, I32, I32, P, SZ, P], I32),
+        "lor_sort_pairs_u64": ([P, P, I64, I32, I32, P, SZ, P], I32),
+        "lor_timing_enable": ([I32], None),
+        "lor_timing_reset": ([], None),
+        "lor_timing_read": ([ctypes.POINTER(lor_timing), I32], I32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _status_string(s: int) -> str:
+    try:
+        return lib().lor_status_string(s).decode()
+    except Exception:
+        return "?"
+
+
+def _check(fn: str, status: int):
+    if status != LOR_OK:
+        raise LorError(fn, status, lib().lor_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+
+
+def _workspace(nbytes: int, device, ws=None):
+    import torch
+    if ws is not None:
+        if ws.numel() * ws.element_size() < nbytes:
+            raise ValueError(f"workspace holds {ws.numel() * ws.element_size()} bytes, {nbytes} needed")
+        return ws
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def _need(t, dtype, n, name):
+    import torch
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or t.numel() < n:
+        raise ValueError(f"{name}: need a contiguous {dtype} device tensor of >= {n} elements")
+
+
+def _offsets(offsets) -> np.ndarray:
+    o = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    if o.ndim != 1 or o.size < 2:
+        raise ValueError("offsets: need int64[num_seqs + 1]")
+    return o
+
+
+# ----------------------------------------------------------- suffix array
+
+def lor_build_sa_workspace(total_bases: int, num_seqs: int) -> int:
+    return int(lib().lor_build_sa_workspace(total_bases, num_seqs))
+
+
+def lor_build_sa(seqs, offsets, joined_out=None, sa_out=None, ws=None, stream=None):
+    """Suffix array of the separator-joined text. Returns (sa, joined)."""
+    import torch
+    o = _offsets(offsets)
+    k = o.size - 1
+    N = int(o[-1]) + k
+    dev = seqs.device
+    _need(seqs, torch.uint8, int(o[-1]), "seqs")
+    if joined_out is None:
+        joined_out = torch.empty(max(N, 1), dtype=torch.uint8, device=dev)
+    if sa_out is None:
+        sa_out = torch.empty(max(N, 1), dtype=torch.int32, device=dev)
+    _need(joined_out, torch.uint8, N, "joined_out")
+    _need(sa_out, torch.int32, N, "sa_out")
+    nbytes = lor_build_sa_workspace(int(o[-1]), k)
+    ws = _workspace(nbytes, dev, ws)
+    st = lib().lor_build_sa(_ptr(seqs), o.ctypes.data_as(ctypes.c_void_p), k, _ptr(joined_out), _ptr(sa_out),
+                            _ptr(ws), ws.numel() * ws.element_size(), _stream(stream))
+    _check("lor_build_sa", st)
+    return sa_out[:N], joined_out[:N]
+
+
+def lor_suffix_array_workspace(n: int) -> int:
+    return int(lib().lor_suffix_array_workspace(n))
+
+
+def lor_suffix_array_i32(text, alphabet_max: int, sa_out=None, ws=None, stream=None):
+    """DC3 suffix array of an int32 text with symbols in 1..alphabet_max."""
+    import torch
+    n = text.numel()
+    _need(text, torch.int32, n, "text")
+    if sa_out is None:
+        sa_out = torch.empty(max(n, 1), dtype=torch.int32, device=text.device)
+    _need(sa_out, torch.int32, n, "sa_out")
+    nbytes = lor_suffix_array_workspace(n)
+    ws = _workspace(nbytes, text.device, ws)
+    st = lib().lor_suffix_array_i32(_ptr(text), n, int(alphabet_max), _ptr(sa_out), _ptr(ws),
+                                    ws.numel() * ws.element_size(), _stream(stream))
+    _check("lor_suffix_array_i32", st)
+    return sa_out[:n]
+
+
+# -------------------------------------------------------------------- LCP
+
+def lor_build_lcp_workspace(n: int) -> int:
+    return int(lib().lor_build_lcp_workspace(n))
+
+
+def lor_build_lcp(text, sa, lcp_out=None, isa_out=None, want_isa=False, ws=None, stream=None):
+    """LCP (and optionally ISA) of `text` given its suffix array. Returns (lcp, isa|None)."""
+    import torch
+    n = text.numel()
+    _need(text, torch.uint8, n, "text")
+    _need(sa, torch.int32, n, "sa")
+    if lcp_out is None:
+        lcp_out = torch.empty(max(n, 1), dtype=torch.int32, device=text.device)
+    if isa_out is None and want_isa:
+        isa_out = torch.empty(max(n, 1), dtype=torch.int32, device=text.device)
+    _need(lcp_out, torch.int32, n, "lcp_out")
+    if isa_out is not None:
+        _need(isa_out, torch.int32, n, "isa_out")
+    nbytes = lor_build_lcp_workspace(n)
+    ws = _workspace(nbytes, text.device, ws)
+    st = lib().lor_build_lcp(_ptr(text), n, _ptr(sa), _ptr(lcp_out), _ptr(isa_out), _ptr(ws),
+                             ws.numel() * ws.element_size(), _stream(stream))
+    _check("lor_build_lcp", st)
+    return lcp_out[:n], (isa_out[:n] if isa_out is not None else None)
+
+
+# -------------------------------------------------------------------- RMQ
+
+class Rmq:
+    """A built sparse table: the C handle plus the tensor that owns its memory."""
+
+    def __init__(self, handle: lor_rmq, table):
+        self.handle = handle
+        self.table = table
+
+    @property
+    def n(self):
+        return int(self.handle.n)
+
+    @property
+    def levels(self):
+        return int(self.handle.levels)
+
+
+def lor_rmq_bytes(n: int) -> int:
+    return int(lib().lor_rmq_bytes(n))
+
+
+def lor_rmq_build(lcp, table=None, stream=None) -> Rmq:
+    import torch
+    n = lcp.numel()
+    _need(lcp, torch.int32, n, "lcp")
+    nbytes = lor_rmq_bytes(n)
+    if table is None:
+        table = torch.empty(max(nbytes // 4, 1), dtype=torch.int32, device=lcp.device)
+    h = lor_rmq()
+    st = lib().lor_rmq_build(_ptr(lcp), n, _ptr(table), table.numel() * table.element_size(), ctypes.byref(h),
+                             _stream(stream))
+    _check("lor_rmq_build", st)
+    return Rmq(h, table)
+
+
+def lor_rmq_query(rmq: Rmq, lcp, isa, mode: int, qi, qj, min_out=None, argmin_out=None, want_argmin=False,
+                  stream=None):
+    """mode 0: ranges [qi, qj] of LCP; mode 1: lcp of suffix pairs (qi, qj). Returns (min, argmin|None)."""
+    import torch
+    nq = qi.numel()
+    _need(qi, torch.int32, nq, "qi")
+    _need(qj, torch.int32, nq, "qj")
+    if min_out is None:
+        min_out = torch.empty(max(nq, 1), dtype=torch.int32, device=qi.device)
+    if argmin_out is None and want_argmin:
+        argmin_out = torch.empty(max(nq, 1), dtype=torch.int32, device=qi.device)
+    st = lib().lor_rmq_query(ctypes.byref(rmq.handle), _ptr(lcp), _ptr(isa), int(mode), _ptr(qi), _ptr(qj), nq,
+                             _ptr(min_out), _ptr(argmin_out), _stream(stream))
+    _check("lor_rmq_query", st)
+    return min_out[:nq], (argmin_out[:nq] if argmin_out is not None else None)
+
+
+# --------------------------------------------------------- longest overlap
+
+def lor_longest_overlap_workspace(n: int, num_seqs: int) -> int:
+    return int(lib().lor_longest_overlap_workspace(n, num_seqs))
+
+
+def lor_longest_overlap(sa, lcp, offsets, ws=None, stream=None) -> tuple:
+    """(length, seq_p, off_p, seq_q, off_q) of the longest region shared by two sequences."""
+    o = _offsets(offsets)
+    k = o.size - 1
+    n = int(o[-1]) + k
+    nbytes = lor_longest_overlap_workspace(n, k)
+    ws = _workspace(nbytes, sa.device, ws)
+    out = lor_overlap()
+    st = lib().lor_longest_overlap(_ptr(sa), _ptr(lcp), n, o.ctypes.data_as(ctypes.c_void_p), k, ctypes.byref(out),
+                                   _ptr(ws), ws.numel() * ws.element_size(), _stream(stream))
+    _check("lor_longest_overlap", st)
+    return (int(out.length), int(out.seq_p), int(out.off_p), int(out.seq_q), int(out.off_q))
+
+
+# ------------------------------------------------------------- radix sort
+
+def lor_sort_pairs_workspace(n: int, key_bytes: int) -> int:
+    return int(lib().lor_sort_pairs_workspace(n, key_bytes))
+
+
+def _sort_pairs(fn, key_bytes, keys, vals, bit_lo, bit_hi, ws, stream):
+    import torch
+    n = keys.numel()
+    _need(keys, torch.int32 if key_bytes == 4 else torch.int64, n, "keys")
+    _need(vals, torch.int32, n, "vals")
+    nbytes = lor_sort_pairs_workspace(n, key_bytes)
+    ws = _workspace(nbytes, keys.device, ws)
+    st = getattr(lib(), fn)(_ptr(keys), _ptr(vals), n, int(bit_lo), int(bit_hi), _ptr(ws),
+                            ws.numel() * ws.element_size(), _stream(stream))
+    _check(fn, st)
+    return keys, vals
+
+
+def lor_sort_pairs_u32(keys, vals, bit_lo=0, bit_hi=32, ws=None, stream=None):
+    """Stable in-place sort of (keys: int32 bits, vals: int32) by key bits [bit_lo, bit_hi)."""
+    return _sort_pairs("lor_sort_pairs_u32", 4, keys, vals, bit_lo, bit_hi, ws, stream)
+
+
+def lor_sort_pairs_u64(keys, vals, bit_lo=0, bit_hi=64, ws=None, stream=None):
+    """Stable in-place sort of (keys: int64 bits, vals: int32) by key bits [bit_lo, bit_hi)."""
+    return _sort_pairs("lor_sort_pairs_u64", 8, keys, vals, bit_lo, bit_hi, ws, stream)
+
+
+# ----------------------------------------------------------------- timing
+
+def lor_timing_enable(on: bool = True):
+    lib().lor_timing_enable(1 if on else 0)
+
+
+def lor_timing_reset():
+    lib().lor_timing_reset()
+
+
+def lor_timing_read() -> dict:
+    """{family: {"launches", "ms", "bytes"}} for every kernel family timed since the last reset."""
+    cap = 64
+    arr = (lor_timing * cap)()
+    k = lib().lor_timing_read(arr, cap)
+    return {arr[i].name.decode(): {"launches": int(arr[i].launches), "ms": float(arr[i].ms),
+                                   "bytes": float(arr[i].bytes)} for i in range(min(k, cap))}
+
+
+# ------------------------------------------------------------- whole path
+
+def longest_overlap_region(seqs, offsets, want_isa=False, stream=None):
+    """Join -> SA -> LCP -> overlap on the device. Returns dict with sa, joined, lcp, isa, overlap."""
+    sa, joined = lor_build_sa(seqs, offsets, stream=stream)
+    lcp, isa = lor_build_lcp(joined, sa, want_isa=want_isa, stream=stream)
+    ov = lor_longest_overlap(sa, lcp, offsets, stream=stream)
+    return {"sa": sa, "joined": joined, "lcp": lcp, "isa": isa, "overlap": ov}

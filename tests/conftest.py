@@ -23,3 +23,19 @@ def golden():
             with open(os.path.join(d, f)) as fh:
                 out[f[:-5]] = json.load(fh)
     return out
+
+
+def pytest_collection_modifyitems(config, items):
+    if not any(item.get_closest_marker("gpu") for item in items):
+        return
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except Exception:
+        has_gpu = False
+    if has_gpu:
+        return
+    skip = pytest.mark.skip(reason="no GPU in this environment")
+    for item in items:
+        if item.get_closest_marker("gpu"):
+            item.add_marker(skip)

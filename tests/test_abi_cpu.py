@@ -1,0 +1,95 @@
+"""The C-ABI library loads, exports every function include/lor.h declares,
+and rejects bad arguments on the host. No GPU needed: every call here returns
+before any device work is enqueued."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_1404_3448_amd import lor
+
+
+@pytest.fixture(scope="module")
+def L():
+    return lor.lib()
+
+
+def test_exports_every_declared_function(L):
+    names = lor.header_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_version_and_status_strings(L):
+    assert L.lor_version() == 1
+    for s in range(7):
+        assert L.lor_status_string(s)
+    assert L.lor_status_string(99) == b"unknown status"
+
+
+FAKE = ctypes.c_void_p(1 << 20)        # never dereferenced: validation fails first
+
+
+def offsets(*xs):
+    o = np.array(xs, dtype=np.int64)
+    return o, o.ctypes.data_as(ctypes.c_void_p)
+
+
+def test_build_sa_argument_errors(L):
+    o, op = offsets(0, 5, 9)
+    ws = lor.lor_build_sa_workspace(9, 2)
+    assert ws > 0
+    assert L.lor_build_sa(FAKE, op, 0, None, FAKE, FAKE, ws, None) == lor.LOR_EINVAL        # num_seqs 0
+    assert L.lor_build_sa(FAKE, op, 252, None, FAKE, FAKE, ws, None) == lor.LOR_EINVAL      # > 251
+    bad, bp = offsets(0, 5, 3)
+    assert L.lor_build_sa(FAKE, bp, 2, None, FAKE, FAKE, ws, None) == lor.LOR_EINVAL
+    assert b"decrease" in L.lor_last_error()
+    bad0, b0 = offsets(1, 5, 9)
+    assert L.lor_build_sa(FAKE, b0, 2, None, FAKE, FAKE, ws, None) == lor.LOR_EINVAL
+    assert L.lor_build_sa(FAKE, op, 2, None, None, FAKE, ws, None) == lor.LOR_EINVAL         # sa_out NULL
+    assert L.lor_build_sa(FAKE, op, 2, None, FAKE, FAKE, ws - 1, None) == lor.LOR_EWORKSPACE
+    assert L.lor_build_sa(FAKE, op, 2, None, FAKE, ctypes.c_void_p((1 << 20) + 8), ws, None) == lor.LOR_EINVAL
+    assert L.lor_build_sa(FAKE, op, 2, ctypes.c_void_p((1 << 20) + 1), FAKE, FAKE, ws, None) == lor.LOR_EINVAL
+    big, gp = offsets(0, 1 << 30, (1 << 31) - 2)
+    assert L.lor_build_sa(FAKE, gp, 2, None, FAKE, FAKE, ws, None) == lor.LOR_ETOOLARGE
+
+
+def test_other_argument_errors(L):
+    assert L.lor_suffix_array_i32(FAKE, 10, 0, FAKE, FAKE, 1 << 30, None) == lor.LOR_EINVAL
+    assert L.lor_suffix_array_i32(FAKE, 1 << 31, 4, FAKE, FAKE, 1 << 30, None) == lor.LOR_ETOOLARGE
+    assert L.lor_suffix_array_i32(FAKE, 10, 4, FAKE, FAKE, 16, None) == lor.LOR_EWORKSPACE
+    assert L.lor_build_lcp(None, 10, FAKE, FAKE, None, FAKE, 1 << 30, None) == lor.LOR_EINVAL
+    assert L.lor_build_lcp(FAKE, 10, FAKE, FAKE, None, FAKE, 8, None) == lor.LOR_EWORKSPACE
+    h = lor.lor_rmq()
+    assert L.lor_rmq_build(FAKE, 100, FAKE, 8, ctypes.byref(h), None) == lor.LOR_EWORKSPACE
+    assert L.lor_rmq_query(ctypes.byref(h), FAKE, FAKE, 2, FAKE, FAKE, 5, FAKE, None, None) == lor.LOR_EINVAL
+    h.n = 100
+    h.levels = 3                                    # floor(log2 100) = 6
+    h.table = 1 << 20
+    assert L.lor_rmq_query(ctypes.byref(h), FAKE, FAKE, 1, FAKE, FAKE, 5, FAKE, None, None) == lor.LOR_ESTALE
+    assert L.lor_rmq_query(ctypes.byref(h), FAKE, None, 1, FAKE, FAKE, 5, FAKE, None, None) == lor.LOR_EINVAL
+    o, op = offsets(0, 4, 8)
+    out = lor.lor_overlap()
+    assert L.lor_longest_overlap(FAKE, FAKE, 9, op, 2, ctypes.byref(out), FAKE, 1 << 20, None) == lor.LOR_EINVAL
+    assert L.lor_longest_overlap(FAKE, FAKE, 10, op, 2, ctypes.byref(out), FAKE, 8, None) == lor.LOR_EWORKSPACE
+    assert L.lor_sort_pairs_u32(FAKE, FAKE, 10, 5, 5, FAKE, 1 << 20, None) == lor.LOR_EINVAL
+    assert L.lor_sort_pairs_u32(FAKE, FAKE, 10, 0, 33, FAKE, 1 << 20, None) == lor.LOR_EINVAL
+    assert L.lor_sort_pairs_u64(FAKE, FAKE, 10, 0, 64, FAKE, 16, None) == lor.LOR_EWORKSPACE
+
+
+def test_size_queries():
+    n = (1 << 30) + 16
+    assert lor.lor_rmq_bytes(1) == 0
+    assert lor.lor_rmq_bytes(2) == 4                      # one level, one window
+    assert lor.lor_rmq_bytes(5) == 4 * ((5 - 1) + (5 - 3))
+    levels = n.bit_length() - 1
+    assert lor.lor_rmq_bytes(n) == 4 * sum(n - (1 << k) + 1 for k in range(1, levels + 1))
+    # the DC3 workspace grows linearly (a bound of the level footprints)
+    a = lor.lor_build_sa_workspace(1 << 20, 2)
+    b = lor.lor_build_sa_workspace(1 << 24, 2)
+    assert 10 < b / a < 20
+    assert lor.lor_build_sa_workspace(1 << 30, 16) < 40 * (1 << 30)
+    assert lor.lor_build_sa_workspace((1 << 31), 2) == 0
+    assert lor.lor_build_lcp_workspace(1000) >= 4000
+    assert lor.lor_sort_pairs_workspace(1000, 3) == 0

@@ -1,0 +1,288 @@
+"""Parity of the HIP path against the CPU oracle, element by element.
+
+Every test calls liblor.so through its C-ABI (the ctypes binding) on cuda:0
+and compares with the oracle on the same seeded inputs. Integers only, so
+every comparison is exact.
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from paper_1404_3448_amd import lor, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+# ------------------------------------------------------------ radix sort
+
+def _keys_u32(rng, n, mode):
+    if mode == "wide":
+        return rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    if mode == "dups":
+        return (rng.integers(0, 7, size=n).astype(np.uint32) * np.uint32(0x01010101))
+    return rng.integers(0, 300, size=n).astype(np.uint32) << np.uint32(rng.integers(0, 20))
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 1000, 4095, 4096, 4097, 262147, 1 << 20])
+@pytest.mark.parametrize("bits", [(0, 32), (0, 8), (3, 17), (0, 15)])
+@pytest.mark.parametrize("mode", ["wide", "dups", "skew"])
+def test_sort_pairs_u32(n, bits, mode):
+    say("sort u32", n, bits, mode)
+    rng = np.random.default_rng(n * 7 + bits[0])
+    keys = _keys_u32(rng, n, mode)
+    vals = rng.permutation(n).astype(np.int32)
+    lo, hi = bits
+    digit = (keys.astype(np.uint64) >> np.uint64(lo)) & np.uint64((1 << (hi - lo)) - 1)
+    order = np.argsort(digit, kind="stable")
+    k = dev(keys.view(np.int32))
+    v = dev(vals)
+    lor.lor_sort_pairs_u32(k, v, lo, hi)
+    assert np.array_equal(host(k).view(np.uint32), keys[order])
+    assert np.array_equal(host(v), vals[order])
+
+
+@pytest.mark.parametrize("n", [1, 100, 3073, 200001])
+@pytest.mark.parametrize("bits", [(0, 64), (5, 45), (0, 21)])
+def test_sort_pairs_u64(n, bits):
+    say("sort u64", n, bits)
+    rng = np.random.default_rng(n + bits[1])
+    keys = rng.integers(0, 1 << 63, size=n, dtype=np.uint64) | (rng.integers(0, 2, size=n, dtype=np.uint64) << np.uint64(63))
+    keys[rng.random(n) < 0.3] = keys[0]
+    vals = np.arange(n, dtype=np.int32)
+    lo, hi = bits
+    mask = np.uint64((1 << (hi - lo)) - 1) if hi - lo < 64 else np.uint64(0xFFFFFFFFFFFFFFFF)
+    digit = (keys >> np.uint64(lo)) & mask
+    order = np.argsort(digit, kind="stable")
+    k = dev(keys.view(np.int64))
+    v = dev(vals)
+    lor.lor_sort_pairs_u64(k, v, lo, hi)
+    assert np.array_equal(host(k).view(np.uint64), keys[order])
+    assert np.array_equal(host(v), vals[order])
+
+
+def test_sort_pairs_split_example(golden):
+    """One 1-bit pass reproduces the split example of Section IV."""
+    g = golden["paper_examples"]["split_example"]
+    k = dev(np.array(g["keys"], dtype=np.int32))
+    v = dev(np.arange(5, dtype=np.int32))
+    lor.lor_sort_pairs_u32(k, v, g["bit"], g["bit"] + 1)
+    assert list(host(k)) == g["out"]
+    dest = np.empty(5, dtype=np.int64)
+    dest[host(v)] = np.arange(5)
+    assert list(dest) == g["dest"]
+
+
+# ------------------------------------------------------------- DC3 core
+
+def sa_i32(text, alphabet):
+    return host(lor.lor_suffix_array_i32(dev(np.asarray(text, dtype=np.int32)), alphabet))
+
+
+def test_dc3_paper_table1(golden):
+    g = golden["paper_examples"]
+    t = [{"A": 1, "C": 2, "G": 3, "T": 4}[c] for c in g["text"]]
+    assert list(sa_i32(t, 4)) == g["table1_sa"]["value"]
+
+
+def test_dc3_all_short_binary_texts():
+    for n in range(1, 9):
+        for t in itertools.product([1, 2], repeat=n):
+            assert list(sa_i32(t, 2)) == brute.suffix_array(list(t)), t
+
+
+@pytest.mark.parametrize("alphabet", [1, 2, 4, 255, 4096, (1 << 20) + 1, (1 << 30) + 7])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 97, 1000, 4099, 70001])
+def test_dc3_random_texts(alphabet, n):
+    say("dc3", alphabet, n)
+    rng = np.random.default_rng(alphabet * 31 + n)
+    t = rng.integers(1, alphabet + 1, size=n).astype(np.int32)
+    assert np.array_equal(sa_i32(t, alphabet), oracle.suffix_array(t))
+
+
+@pytest.mark.parametrize("period", [1, 2, 3, 5, 7, 12])
+@pytest.mark.parametrize("n", [10, 999, 30001])
+def test_dc3_periodic_texts(period, n):
+    """Long repeats force deep recursion (A^n recurses about log_1.5 n times)."""
+    say("dc3 periodic", period, n)
+    rng = np.random.default_rng(period * 1000 + n)
+    unit = rng.integers(1, 4, size=period).astype(np.int32)
+    t = np.resize(unit, n)
+    if n > 100:
+        hit = rng.integers(0, n, size=3)
+        t[hit] = 4
+    assert np.array_equal(sa_i32(t, 4), oracle.suffix_array(t))
+
+
+# ----------------------------------------------------------- joined text
+
+def build(seqs):
+    seqs = [np.asarray(s, dtype=np.uint8) for s in seqs]
+    offs = np.concatenate([[0], np.cumsum([s.size for s in seqs])]).astype(np.int64)
+    cat = np.concatenate(seqs) if sum(s.size for s in seqs) else np.zeros(1, np.uint8)
+    return dev(cat), offs
+
+
+def test_build_sa_joined_example(golden):
+    g = golden["paper_examples"]
+    seqs, offs = build([synth.encode(g["text"])])
+    sa, joined = lor.lor_build_sa(seqs, offs)
+    assert list(host(joined)) == list(synth.encode(g["text"])) + [4]
+    assert list(host(sa)) == g["joined_example"]["sa"]
+    lcp, isa = lor.lor_build_lcp(joined, sa, want_isa=True)
+    assert list(host(lcp)) == g["joined_example"]["lcp"]
+    assert list(host(isa)) == list(oracle.isa(np.array(g["joined_example"]["sa"], np.int32)))
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_build_sa_lcp_many_sequences(seed):
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(1, 9)) if seed < 12 else int(rng.integers(100, 252))
+    alpha = int(rng.integers(1, 5))
+    seqs = [rng.integers(0, alpha, size=int(rng.integers(0, 3000)), dtype=np.uint8) for _ in range(k)]
+    if seed % 4 == 0:
+        seqs[0] = np.zeros(0, np.uint8)
+    say("build_sa", seed, k, [s.size for s in seqs][:8])
+    d, offs = build(seqs)
+    sa, joined = lor.lor_build_sa(d, offs)
+    want_joined = oracle.join(np.concatenate(seqs), offs)
+    assert np.array_equal(host(joined), want_joined)
+    want_sa = oracle.suffix_array(want_joined)
+    assert np.array_equal(host(sa), want_sa)
+    lcp, isa = lor.lor_build_lcp(joined, sa, want_isa=True)
+    assert np.array_equal(host(lcp), oracle.lcp(want_joined, want_sa))
+    assert np.array_equal(host(isa), oracle.isa(want_sa))
+    ov = lor.lor_longest_overlap(sa, lcp, offs)
+    assert ov == oracle.overlap(want_sa, oracle.lcp(want_joined, want_sa), offs)
+
+
+def test_build_sa_rejects_bad_base():
+    d, offs = build([[0, 1, 2], [3, 7, 1]])
+    with pytest.raises(lor.LorError) as e:
+        lor.lor_build_sa(d, offs)
+    assert e.value.status == lor.LOR_EALPHABET
+
+
+def test_repeated_calls_are_bit_identical():
+    w = synth.noncoding_pair(seed=21, n=300_000, segments=4)
+    d, offs = dev(w.concat), w.offsets
+    sa1, j1 = lor.lor_build_sa(d, offs)
+    l1, _ = lor.lor_build_lcp(j1, sa1)
+    first = (host(sa1).copy(), host(l1).copy())
+    for _ in range(2):
+        sa2, j2 = lor.lor_build_sa(d, offs)
+        l2, _ = lor.lor_build_lcp(j2, sa2)
+        assert np.array_equal(host(sa2), first[0]) and np.array_equal(host(l2), first[1])
+
+
+# --------------------------------------------------------------- overlap
+
+@pytest.mark.parametrize("case", range(8))
+def test_overlap_closed_forms(golden, case):
+    c = golden["overlap_closed_forms"]["cases"][case]
+    d, offs = build([synth.encode(c["a"]), synth.encode(c["b"])])
+    r = lor.longest_overlap_region(d, offs)
+    assert list(r["overlap"]) == c["expect"]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_overlap_brute_force(seed):
+    rng = np.random.default_rng(300 + seed)
+    k = int(rng.integers(2, 5))
+    alpha = int(rng.integers(1, 5))
+    seqs = [rng.integers(0, alpha, size=int(rng.integers(0, 30)), dtype=np.uint8) for _ in range(k)]
+    d, offs = build(seqs)
+    r = lor.longest_overlap_region(d, offs)
+    assert r["overlap"] == brute.longest_overlap(seqs)
+
+
+def test_tiny_pair_workload():
+    """50k + 50k uniform bases with a planted 500-base copy: SA, LCP and the
+    overlap equal the oracle's; the overlap equals the O(nm) DP's."""
+    w = synth.tiny_pair()
+    d = dev(w.concat)
+    r = lor.longest_overlap_region(d, w.offsets, want_isa=True)
+    joined = oracle.join(w.concat, w.offsets)
+    want_sa = oracle.suffix_array(joined)
+    want_lcp = oracle.lcp(joined, want_sa)
+    assert np.array_equal(host(r["joined"]), joined)
+    assert np.array_equal(host(r["sa"]), want_sa)
+    assert np.array_equal(host(r["lcp"]), want_lcp)
+    L, sp, op, sq, oq = r["overlap"]
+    assert r["overlap"] == oracle.overlap(want_sa, want_lcp, w.offsets)
+    assert (L, op, oq) == oracle.lcs_dp(w.seqs[0], w.seqs[1])
+    assert L >= 500
+
+
+# ------------------------------------------------------------------- RMQ
+
+@pytest.mark.parametrize("n_bases", [3, 17, 1000, 40000])
+def test_rmq_range_and_pair_queries(n_bases):
+    rng = np.random.default_rng(n_bases)
+    w = synth.noncoding_pair(seed=n_bases, n=n_bases, segments=2, seg_lo=2, seg_hi=max(3, n_bases // 3))
+    d = dev(w.concat)
+    r = lor.longest_overlap_region(d, w.offsets, want_isa=True)
+    joined = oracle.join(w.concat, w.offsets)
+    n = joined.size
+    lcp_h = host(r["lcp"])
+    rmq = lor.lor_rmq_build(r["lcp"])
+    assert rmq.levels == n.bit_length() - 1
+    lo = rng.integers(0, n, size=3000)
+    hi = np.minimum(n - 1, lo + rng.integers(0, n, size=3000) % (1 + rng.integers(1, n + 1, size=3000)))
+    mn, am = lor.lor_rmq_query(rmq, r["lcp"], r["isa"], 0, dev(lo.astype(np.int32)), dev(hi.astype(np.int32)),
+                               want_argmin=True)
+    mn, am = host(mn), host(am)
+    for k in range(lo.size):
+        assert (mn[k], am[k]) == oracle.range_min(lcp_h, lo[k], hi[k])
+    qi = rng.integers(0, n, size=5000).astype(np.int32)
+    qj = rng.integers(0, n, size=5000).astype(np.int32)
+    qj[:50] = qi[:50]
+    got, _ = lor.lor_rmq_query(rmq, r["lcp"], r["isa"], 1, dev(qi), dev(qj))
+    assert np.array_equal(host(got), oracle.pair_queries(joined, qi, qj))
+    bad_i = np.array([-1, n, 0, 5 % n], dtype=np.int32)
+    bad_j = np.array([0, 0, n + 3, -7], dtype=np.int32)
+    got, am = lor.lor_rmq_query(rmq, r["lcp"], r["isa"], 1, dev(bad_i), dev(bad_j), want_argmin=True)
+    assert list(host(got)) == [-1] * 4 and list(host(am)) == [-1] * 4
+    got, _ = lor.lor_rmq_query(rmq, r["lcp"], r["isa"], 0, dev(np.array([3 % n], np.int32)),
+                               dev(np.array([0], np.int32)))
+    assert list(host(got)) == ([-1] if 3 % n > 0 else [0])
+
+
+# ------------------------------------------------------- larger workloads
+
+def test_noncoding_pair_8m():
+    """The 8M + 8M workload at full size: SA and LCP equal the oracle's
+    (comparison sort + direct LCP), and so does the overlap."""
+    w = synth.noncoding_pair()
+    say("8M+8M generated")
+    d = dev(w.concat)
+    r = lor.longest_overlap_region(d, w.offsets)
+    joined = oracle.join(w.concat, w.offsets)
+    want_sa = oracle.suffix_array(joined)
+    want_lcp = oracle.lcp(joined, want_sa)
+    say("8M+8M oracle done")
+    assert np.array_equal(host(r["sa"]), want_sa)
+    assert np.array_equal(host(r["lcp"]), want_lcp)
+    assert r["overlap"] == oracle.overlap(want_sa, want_lcp, w.offsets)
