@@ -1,0 +1,206 @@
+"""Benchmark of the longest-overlap-region path on one MI355X.
+
+One step = the whole path over one text already resident in HBM:
+join -> DC3 suffix array -> LCP (+ ISA) -> sparse-table RMQ build ->
+10M suffix-pair lcp queries -> longest overlap scan.
+
+Default workload: 16 noncoding-like sequences of 67,108,864 bases (40% GC,
+tandem repeats over ~10% of each), joined length N = 1,073,741,840, with
+10,000,000 uniform (i, j) queries (seed 3). `value` is N / step time in
+Msuffixes/s for the whole step; the SA+LCP-only rate is reported beside it.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DC3 SA+LCP Msuffixes/s at 1G bases; batched pairs/s vs plain, bit-exact"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (num_seqs, seq_len, num_queries)
+    "1g": (16, 1 << 26, 10_000_000),
+    "8m": (2, 1 << 23, 1_000_000),
+    "1m": (2, 1 << 20, 100_000),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(seqs, seq_cut: int, nseq: int, threads: int) -> dict:
+    """The CPU oracle (comparison-sort SA, direct LCP, overlap scan) on the
+    first `nseq` sequences cut to `seq_cut` bases each."""
+    import oracle
+
+    sub = [s[:seq_cut] for s in seqs[:nseq]]
+    offs = np.concatenate([[0], np.cumsum([s.size for s in sub])]).astype(np.int64)
+    cat = np.concatenate(sub)
+    t0 = time.perf_counter()
+    joined = oracle.join(cat, offs)
+    sa = oracle.suffix_array(joined, nthreads=threads)
+    lcp = oracle.lcp(joined, sa, nthreads=threads)
+    oracle.overlap(sa, lcp, offs)
+    dt = time.perf_counter() - t0
+    return {"value": round(joined.size / dt / 1e6, 3), "unit": "Msuffixes/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {nseq} sequences cut to {seq_cut} bases (N = {joined.size}); join + "
+                      f"comparison-sort SA + direct LCP + overlap scan, {dt:.2f} s",
+            "seconds": round(dt, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="1g", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1404_3448_amd import lor, synth
+
+    num_seqs, seq_len, nq = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    w = synth.long_text(seed=3, num_seqs=num_seqs, seq_len=seq_len, num_queries=nq)
+    log(f"generated {w.name} in {time.perf_counter() - t0:.1f} s")
+    offsets = w.offsets
+    N = w.joined_length
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    seqs = torch.from_numpy(w.concat).to(dev)
+    qi = torch.from_numpy(w.queries[0]).to(dev)
+    qj = torch.from_numpy(w.queries[1]).to(dev)
+    joined = torch.empty(N, dtype=torch.uint8, device=dev)
+    sa = torch.empty(N, dtype=torch.int32, device=dev)
+    lcp = torch.empty(N, dtype=torch.int32, device=dev)
+    isa = torch.empty(N, dtype=torch.int32, device=dev)
+    qout = torch.empty(nq, dtype=torch.int32, device=dev)
+    ws_sa = torch.empty(lor.lor_build_sa_workspace(int(offsets[-1]), num_seqs), dtype=torch.uint8, device=dev)
+    ws_lcp = torch.empty(lor.lor_build_lcp_workspace(N), dtype=torch.uint8, device=dev)
+    ws_ov = torch.empty(lor.lor_longest_overlap_workspace(N, num_seqs), dtype=torch.uint8, device=dev)
+    table = torch.empty(lor.lor_rmq_bytes(N) // 4, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    log(f"allocated {torch.cuda.memory_allocated() / 2**30:.1f} GiB on {torch.cuda.get_device_name(dev)}")
+
+    names = ["sa", "lcp", "rmq_build", "queries", "overlap"]
+
+    def step(ev=None):
+        if ev:
+            ev[0].record()
+        lor.lor_build_sa(seqs, offsets, joined_out=joined, sa_out=sa, ws=ws_sa)
+        if ev:
+            ev[1].record()
+        lor.lor_build_lcp(joined, sa, lcp_out=lcp, isa_out=isa, ws=ws_lcp)
+        if ev:
+            ev[2].record()
+        rmq = lor.lor_rmq_build(lcp, table=table)
+        if ev:
+            ev[3].record()
+        lor.lor_rmq_query(rmq, lcp, isa, 1, qi, qj, min_out=qout)
+        if ev:
+            ev[4].record()
+        ov = lor.lor_longest_overlap(sa, lcp, offsets, ws=ws_ov)
+        if ev:
+            ev[5].record()
+        return ov
+
+    for i in range(args.warmup):
+        t = time.perf_counter()
+        ov = step()
+        torch.cuda.synchronize()
+        log(f"warmup {i}: {1e3 * (time.perf_counter() - t):.1f} ms, overlap {ov}")
+
+    if not args.no_kernel_timing:
+        lor.lor_timing_reset()
+        lor.lor_timing_enable(True)
+    stage_ms = {k: 0.0 for k in names}
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        ov = step(ev)
+        ev[5].synchronize()
+        for k, name in enumerate(names):
+            stage_ms[name] += ev[k].elapsed_time(ev[k + 1])
+        log(f"step {i}: {ev[0].elapsed_time(ev[5]):.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    kernels = {}
+    if not args.no_kernel_timing:
+        kernels = lor.lor_timing_read()
+        lor.lor_timing_enable(False)
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = N / (elapsed / args.steps) / 1e6
+    stages = {k: round(v / args.steps, 3) for k, v in stage_ms.items()}
+    sa_lcp_ms = stages["sa"] + stages["lcp"]
+
+    roofline = None
+    kern_out = {}
+    for name, k in sorted(kernels.items(), key=lambda kv: -kv[1]["ms"]):
+        gbs = k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0
+        kern_out[name] = {"launches_per_step": k["launches"] / args.steps, "ms_per_step": round(k["ms"] / args.steps, 3),
+                          "alg_GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    if kernels:
+        dom_name, dom = max(kernels.items(), key=lambda kv: kv[1]["ms"])
+        achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom_name,
+                    "launch_ms_avg": round(dom["ms"] / dom["launches"], 4),
+                    "alg_bytes_per_launch_avg": round(dom["bytes"] / dom["launches"])}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        cut = min(seq_len, 1 << 24)
+        log("timing the CPU oracle sample ...")
+        cpu = cpu_baseline(w.seqs, cut, min(4, num_seqs), threads)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Msuffixes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{num_seqs} x {seq_len}-base noncoding-like sequences (40% GC, tandem repeats), "
+                               f"joined N = {N}; SA + LCP + ISA + sparse-table RMQ + {nq} suffix-pair queries + "
+                               f"longest overlap",
+                   "num_seqs": num_seqs, "seq_len": seq_len, "joined_length": N, "queries": nq, "seed": 3},
+        "sa_lcp_msuffixes_per_s": round(N / (sa_lcp_ms * 1e-3) / 1e6, 3),
+        "queries_per_s": round(nq / (stages["queries"] * 1e-3), 1) if stages["queries"] > 0 else None,
+        "stages_ms": stages,
+        "overlap": list(ov),
+        "roofline": roofline,
+        "kernels": kern_out,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
