@@ -2,6 +2,7 @@
 // per-thread error text and the optional kernel-family timing registry.
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <vector>
@@ -19,18 +20,25 @@ struct Pending {
     double bytes;
 };
 struct FamilyStat {
+    const char *name = nullptr;
     int64_t launches = 0;
     double ms = 0;
     double bytes = 0;
 };
+constexpr int kMaxFamilies = 96;
 bool g_timing = false;
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_event_pool;
-FamilyStat g_stats[F_NUM];
-const char *kFamilyNames[F_NUM] = {"join", "sample_keys", "radix_count", "radix_scan", "radix_scatter",
-                                   "naming", "rank_scatter", "merge_records", "nonsample", "merge_partition",
-                                   "merge", "phi", "plcp", "lcp_permute", "sparse_table", "rmq_query",
-                                   "overlap_scan", "misc"};
+FamilyStat g_stats[kMaxFamilies];
+int g_nfam = 0;
+
+int family_of(const char *name) {
+    for (int i = 0; i < g_nfam; ++i)
+        if (g_stats[i].name == name || strcmp(g_stats[i].name, name) == 0) return i;
+    if (g_nfam == kMaxFamilies) return kMaxFamilies - 1;
+    g_stats[g_nfam].name = name;
+    return g_nfam++;
+}
 
 hipEvent_t take_event() {
     if (!g_event_pool.empty()) {
@@ -67,7 +75,13 @@ void set_error(const char *fmt, ...) {
 
 bool timing_on() { return g_timing; }
 
-int timing_begin(hipStream_t s, Family f, double bytes) {
+bool trace_on() {
+    static const bool on = getenv("LOR_TRACE") != nullptr;
+    return on;
+}
+
+int timing_begin(hipStream_t s, const char *kernel, double bytes) {
+    const int f = family_of(kernel);
     if (g_pending.size() > 100000) drain_pending();
     Pending p;
     p.a = take_event();
@@ -376,17 +390,21 @@ void lor_timing_enable(int32_t on) { g_timing = on != 0; }
 
 void lor_timing_reset(void) {
     drain_pending();
-    for (auto &f : g_stats) f = FamilyStat();
+    for (int i = 0; i < g_nfam; ++i) {
+        const char *nm = g_stats[i].name;
+        g_stats[i] = FamilyStat();
+        g_stats[i].name = nm;
+    }
 }
 
 int32_t lor_timing_read(lor_timing *out, int32_t cap) {
     drain_pending();
     int32_t w = 0;
-    for (int f = 0; f < F_NUM; ++f) {
+    for (int f = 0; f < g_nfam; ++f) {
         if (!g_stats[f].launches) continue;
         if (out && w < cap) {
             memset(&out[w], 0, sizeof(lor_timing));
-            strncpy(out[w].name, kFamilyNames[f], sizeof(out[w].name) - 1);
+            strncpy(out[w].name, g_stats[f].name, sizeof(out[w].name) - 1);
             out[w].launches = g_stats[f].launches;
             out[w].ms = g_stats[f].ms;
             out[w].bytes = g_stats[f].bytes;

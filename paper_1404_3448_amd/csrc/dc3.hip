@@ -25,6 +25,8 @@
 // triple q = (t_3q..t_3q+3, rank(3q+1), rank(3q+2), rank(3q+4)); every merge
 // element (mod 0, 1 or 2) then needs exactly one record gather, and the
 // merge-path partitioning keeps each workgroup on a fixed output tile.
+#include <stdio.h>
+
 #include "lor_internal.hpp"
 
 namespace lor {
@@ -183,12 +185,14 @@ __global__ __launch_bounds__(kBlock) void k_name_count(const CH *__restrict__ t,
     if (threadIdx.x == 0) counts[blockIdx.x] = tot;
 }
 
+// names[r] = 1-based name of sorted entry r (written in sorted order; a
+// bucketed scatter then moves each name to its R-index).
 template <typename CH, typename K, bool GATHER>
 __global__ __launch_bounds__(kBlock) void k_name_write(const CH *__restrict__ t, Dims d,
                                                        const K *__restrict__ keys,
                                                        const uint32_t *__restrict__ vals,
                                                        uint32_t groups, const uint32_t *__restrict__ counts,
-                                                       int32_t *__restrict__ R) {
+                                                       uint32_t *__restrict__ names) {
     __shared__ uint32_t s_tmp[kBlock / kWave];
     uint32_t t0, t1;
     group_tiles(d.m, groups, blockIdx.x, &t0, &t1);
@@ -216,21 +220,75 @@ __global__ __launch_bounds__(kBlock) void k_name_write(const CH *__restrict__ t,
             const uint32_t r = r0 + i;
             if (r < d.m) {
                 name += f[i];
-                const uint32_t ri = vals[r];
-                if (ri < d.m) R[ri] = (int32_t)name;
+                names[r] = name;
             }
         }
         base += tot;
     }
 }
 
-// rank12[sa12[r]] = r + 1
-__global__ __launch_bounds__(kBlock) void k_rank_from_sa(const int32_t *__restrict__ sa12, uint32_t m,
-                                                         int32_t *__restrict__ rank12) {
-    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < m; r += gridDim.x * kBlock)
-    {
-        const uint32_t ri = (uint32_t)sa12[r];
-        if (ri < m) rank12[ri] = (int32_t)(r + 1);
+// ------------------------------------ Step 1: naming by a key bitmap
+
+// When the packed triple keys span at most 2^24 values and that span is not
+// much larger than the number of sample positions, lexicographic names need no
+// sort: mark every key present in a bitmap, prefix-count the marks, and the
+// name of a key is 1 + the number of present keys below it. Names are then
+// written in R-index order (streaming) instead of scattered from sorted order.
+template <typename CH>
+__device__ __forceinline__ uint32_t triple_key(const CH *t, const Dims &d, int b, uint32_t idx) {
+    const uint32_t p = d.pos_of(idx);
+    return (sym(t, d.n, p) << (2 * b)) | (sym(t, d.n, p + 1) << b) | sym(t, d.n, p + 2);
+}
+
+template <typename CH>
+__global__ __launch_bounds__(kBlock) void k_presence(const CH *__restrict__ t, Dims d, int b,
+                                                     uint32_t *__restrict__ bitmap, uint32_t words, int in_lds) {
+    extern __shared__ uint32_t s_bits[];
+    if (in_lds) {
+        for (uint32_t w = threadIdx.x; w < words; w += kBlock) s_bits[w] = 0;
+        __syncthreads();
+    }
+    for (uint32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < d.m; idx += gridDim.x * kBlock) {
+        const uint32_t key = triple_key(t, d, b, idx);
+        const uint32_t w = key >> 5, bit = 1u << (key & 31u);
+        if (w >= words) continue;
+        if (in_lds) {
+            if (!(s_bits[w] & bit)) atomicOr(&s_bits[w], bit);
+        } else if (!(bitmap[w] & bit)) {
+            atomicOr(&bitmap[w], bit);   // a stale read only costs a redundant atomic
+        }
+    }
+    if (in_lds) {
+        __syncthreads();
+        for (uint32_t w = threadIdx.x; w < words; w += kBlock)
+            if (s_bits[w]) atomicOr(&bitmap[w], s_bits[w]);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_popc(const uint32_t *__restrict__ bitmap, uint32_t words,
+                                                 uint32_t *__restrict__ cnt) {
+    for (uint32_t w = blockIdx.x * kBlock + threadIdx.x; w < words; w += gridDim.x * kBlock)
+        cnt[w] = (uint32_t)__popc(bitmap[w]);
+}
+
+template <typename CH>
+__global__ __launch_bounds__(kBlock) void k_name_table(const CH *__restrict__ t, Dims d, int b,
+                                                       const uint32_t *__restrict__ bitmap,
+                                                       const uint32_t *__restrict__ below, uint32_t words,
+                                                       int32_t *__restrict__ R) {
+    for (uint32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < d.m; idx += gridDim.x * kBlock) {
+        const uint32_t key = triple_key(t, d, b, idx);
+        const uint32_t w = min(key >> 5, words - 1);
+        R[idx] = (int32_t)(below[w] + (uint32_t)__popc(bitmap[w] & ((1u << (key & 31u)) - 1u)) + 1u);
+    }
+}
+
+// Unique names are ranks: sa12[name - 1] = R-index.
+__global__ __launch_bounds__(kBlock) void k_sa12_from_names(const int32_t *__restrict__ R, uint32_t m,
+                                                            int32_t *__restrict__ sa12) {
+    for (uint32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < m; idx += gridDim.x * kBlock) {
+        const uint32_t r = (uint32_t)R[idx] - 1u;
+        if (r < m) sa12[r] = (int32_t)idx;
     }
 }
 
@@ -487,12 +545,36 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     const uint32_t g_el = grid_for(d.m);
     uint32_t hmax = 0;
 
-    if (km == KM_U64) {
+    const int kb = 3 * b;
+    const bool use_table = run && kb <= 24 && ((uint64_t)1 << kb) <= 2ull * d.m + 65536ull;
+    if (use_table) {
+        const uint32_t words = max(1u, (uint32_t)(((uint64_t)1 << kb) / 32));
+        uint32_t *bitmap, *below, *stmp;
+        LOR_TAKE(ar, uint32_t, words, bitmap);
+        LOR_TAKE(ar, uint32_t, words, below);
+        LOR_TAKE(ar, uint32_t, kScanTmpWords, stmp);
+        LOR_TRY(zero_words(bitmap, words, s));
+        const int in_lds = words <= 8192;
+        LOR_LAUNCH("k_presence", (double)n * sizeof(CH), s,
+                   hipLaunchKernelGGL(k_presence<CH>, dim3(in_lds ? min(grid_for(d.m), 2048u) : grid_for(d.m)),
+                                      dim3(kBlock), in_lds ? words * 4 : 0, s, t, d, b, bitmap, words, in_lds));
+        LOR_LAUNCH("k_popc", 8.0 * words, s,
+                   hipLaunchKernelGGL(k_popc, dim3(grid_for(words)), dim3(kBlock), 0, s, bitmap, words, below));
+        LOR_TRY(scan_exclusive(below, words, stmp, hdr + 1, s));
+        LOR_LAUNCH("k_name_table", (double)n * sizeof(CH) + 4.0 * d.m, s,
+                   hipLaunchKernelGGL(k_name_table<CH>, dim3(g_el), dim3(kBlock), 0, s, t, d, b, bitmap, below, words,
+                                      R));
+    } else if (km == KM_U64) {
         uint64_t *k0, *k1;
         LOR_TAKE(ar, uint64_t, d.m, k0);
         LOR_TAKE(ar, uint64_t, d.m, k1);
+        if (!run) {
+            // the bitmap path may take up to 2 x (2m + 65536) / 32 words plus scan space
+            uint8_t *extra;
+            LOR_TAKE(ar, uint8_t, (size_t)d.m / 2 + 16384 + kScanTmpWords * 4 + 1024, extra);
+        }
         if (run) {
-            LOR_LAUNCH(F_KEYS, (double)d.m * 12 + (double)n * sizeof(CH), s,
+            LOR_LAUNCH("k_sample_keys", (double)d.m * 12 + (double)n * sizeof(CH), s,
                        hipLaunchKernelGGL((k_sample_keys<CH, uint64_t>), dim3(g_el), dim3(kBlock), 0, s, t, d, b,
                                           0, 0, k0, v0));
             bool alt;
@@ -502,19 +584,25 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
                 set_error("internal: sorted sample order not in its buffer");
                 return LOR_EINVAL;
             }
+            // free now: the other key buffer (2 x m words) and the other value buffer
+            uint32_t *names = reinterpret_cast<uint32_t *>(alt ? k0 : k1);
+            uint32_t *tmp_idx = names + d.m;
+            uint32_t *tmp_val = alt ? v0 : v1;
             const uint32_t G = scan_groups(d.m);
-            LOR_LAUNCH(F_NAME, (double)d.m * 8, s,
+            LOR_LAUNCH("k_name_count", (double)d.m * 8, s,
                        hipLaunchKernelGGL((k_name_count<CH, uint64_t, false>), dim3(G), dim3(kBlock), 0, s, t, d,
                                           ks, (const uint32_t *)sa12, G, gcount));
             LOR_TRY(scan_block_totals(gcount, G, hdr + 1, s));
-            LOR_LAUNCH(F_NAME, (double)d.m * 16, s,
+            LOR_LAUNCH("k_name_write", (double)d.m * 12, s,
                        hipLaunchKernelGGL((k_name_write<CH, uint64_t, false>), dim3(G), dim3(kBlock), 0, s, t, d,
-                                          ks, (const uint32_t *)sa12, G, gcount, R));
+                                          ks, (const uint32_t *)sa12, G, gcount, names));
+            LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, names, 0, d.m, tmp_idx, tmp_val, counts, s));
         }
     } else {
-        uint32_t *k0, *k1;
+        uint32_t *k0, *k1, *aux;
         LOR_TAKE(ar, uint32_t, d.m, k0);
         LOR_TAKE(ar, uint32_t, d.m, k1);
+        LOR_TAKE(ar, uint32_t, d.m, aux);
         if (run) {
             bool alt = false;
             uint32_t *kc = k0, *ka = k1, *vc = v0, *va = v1;
@@ -522,20 +610,20 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
                 if (a) { uint32_t *x = kc; kc = ka; ka = x; x = vc; vc = va; va = x; }
             };
             if (km == KM_U32) {
-                LOR_LAUNCH(F_KEYS, (double)d.m * 8 + (double)n * sizeof(CH), s,
+                LOR_LAUNCH("k_sample_keys", (double)d.m * 8 + (double)n * sizeof(CH), s,
                            hipLaunchKernelGGL((k_sample_keys<CH, uint32_t>), dim3(g_el), dim3(kBlock), 0, s, t, d,
                                               b, 0, 0, kc, vc));
                 LOR_TRY(radix_sort<uint32_t>(kc, vc, ka, va, d.m, 0, 3 * b, counts, s, &alt));
                 swap_if(alt);
             } else {
                 // LSD over whole symbols: t_{i+2}, then t_{i+1}, then t_i.
-                LOR_LAUNCH(F_KEYS, (double)d.m * 8 + (double)d.m * sizeof(CH), s,
+                LOR_LAUNCH("k_sample_keys", (double)d.m * 8 + (double)d.m * sizeof(CH), s,
                            hipLaunchKernelGGL((k_sample_keys<CH, uint32_t>), dim3(g_el), dim3(kBlock), 0, s, t, d,
                                               b, 1, 2, kc, vc));
                 LOR_TRY(radix_sort<uint32_t>(kc, vc, ka, va, d.m, 0, b, counts, s, &alt));
                 swap_if(alt);
                 for (int delta = 1; delta >= 0; --delta) {
-                    LOR_LAUNCH(F_KEYS, (double)d.m * 8 + (double)d.m * sizeof(CH), s,
+                    LOR_LAUNCH("k_rekey", (double)d.m * 8 + (double)d.m * sizeof(CH), s,
                                hipLaunchKernelGGL((k_rekey<CH>), dim3(g_el), dim3(kBlock), 0, s, t, d, delta, vc, kc));
                     LOR_TRY(radix_sort<uint32_t>(kc, vc, ka, va, d.m, 0, b, counts, s, &alt));
                     swap_if(alt);
@@ -545,24 +633,26 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
                 set_error("internal: sorted sample order not in its buffer");
                 return LOR_EINVAL;
             }
+            uint32_t *names = ka, *tmp_idx = va, *tmp_val = aux;
             const uint32_t G = scan_groups(d.m);
             if (km == KM_U32) {
-                LOR_LAUNCH(F_NAME, (double)d.m * 4, s,
+                LOR_LAUNCH("k_name_count", (double)d.m * 4, s,
                            hipLaunchKernelGGL((k_name_count<CH, uint32_t, false>), dim3(G), dim3(kBlock), 0, s, t,
                                               d, kc, vc, G, gcount));
                 LOR_TRY(scan_block_totals(gcount, G, hdr + 1, s));
-                LOR_LAUNCH(F_NAME, (double)d.m * 12, s,
+                LOR_LAUNCH("k_name_write", (double)d.m * 8, s,
                            hipLaunchKernelGGL((k_name_write<CH, uint32_t, false>), dim3(G), dim3(kBlock), 0, s, t,
-                                              d, kc, vc, G, gcount, R));
+                                              d, kc, vc, G, gcount, names));
             } else {
-                LOR_LAUNCH(F_NAME, (double)d.m * 8, s,
+                LOR_LAUNCH("k_name_count", (double)d.m * 8, s,
                            hipLaunchKernelGGL((k_name_count<CH, uint32_t, true>), dim3(G), dim3(kBlock), 0, s, t,
                                               d, kc, vc, G, gcount));
                 LOR_TRY(scan_block_totals(gcount, G, hdr + 1, s));
-                LOR_LAUNCH(F_NAME, (double)d.m * 16, s,
+                LOR_LAUNCH("k_name_write", (double)d.m * 12, s,
                            hipLaunchKernelGGL((k_name_write<CH, uint32_t, true>), dim3(G), dim3(kBlock), 0, s, t,
-                                              d, kc, vc, G, gcount, R));
+                                              d, kc, vc, G, gcount, names));
             }
+            LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, names, 0, d.m, tmp_idx, tmp_val, counts, s));
         }
     }
 
@@ -581,6 +671,13 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
             return LOR_EINVAL;
         }
         unique = (hmax == d.m);
+        if (trace_on())
+            fprintf(stderr, "[lor] dc3 level %d: n=%u m=%u bits/sym=%d %s passes=%d names=%u%s\n", depth, n, d.m, b,
+                    use_table ? "bitmap-naming" : (km == KM_U32 ? "sort-u32" : km == KM_U64 ? "sort-u64" : "sort-staged"),
+                    use_table ? 0 : passes, hmax, unique ? " unique" : "");
+        if (unique && use_table)
+            LOR_LAUNCH("k_sa12_from_names", 12.0 * d.m, s,
+                       hipLaunchKernelGGL(k_sa12_from_names, dim3(g_el), dim3(kBlock), 0, s, R, d.m, sa12));
     } else {
         unique = d.m < 2;
         hmax = d.m;
@@ -589,9 +686,14 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
 
     if (!unique) {
         LOR_TRY(dc3_level<int32_t>(R, d.m, hmax, sa12, ar, hdr, s, depth + 1));
-        if (run)
-            LOR_LAUNCH(F_RANK, (double)d.m * 8, s,
-                       hipLaunchKernelGGL(k_rank_from_sa, dim3(g_el), dim3(kBlock), 0, s, sa12, d.m, R));
+        // rank12[sa12[r]] = r + 1, as a bucketed scatter
+        const size_t mk = ar.mark();
+        uint32_t *ta, *tb, *cr;
+        LOR_TAKE(ar, uint32_t, d.m, ta);
+        LOR_TAKE(ar, uint32_t, d.m, tb);
+        LOR_TAKE(ar, uint32_t, radix_counts_words(d.m), cr);
+        if (run) LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, nullptr, 1, d.m, ta, tb, cr, s));
+        ar.release(mk);
     }
     const int32_t *rank12 = R;
 
@@ -599,7 +701,7 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     Rec<CH> *rec;
     LOR_TAKE(ar, Rec<CH>, (size_t)d.n0 + 1, rec);
     if (run)
-        LOR_LAUNCH(F_RECORDS, (double)(d.n0 + 1) * (sizeof(Rec<CH>) + 12) + (double)n * sizeof(CH), s,
+        LOR_LAUNCH("k_records", (double)(d.n0 + 1) * (sizeof(Rec<CH>) + 12) + (double)n * sizeof(CH), s,
                    hipLaunchKernelGGL(k_records<CH>, dim3(grid_for(d.n0 + 1)), dim3(kBlock), 0, s, t, d, rank12,
                                       rec));
 
@@ -616,10 +718,10 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     LOR_TAKE(ar, uint32_t, (size_t)parts + 1, split);
     if (run) {
         const uint32_t G = scan_groups(d.m);
-        LOR_LAUNCH(F_NONSAMPLE, (double)d.m * 4, s,
+        LOR_LAUNCH("k_ns_count", (double)d.m * 4, s,
                    hipLaunchKernelGGL(k_ns_count, dim3(G), dim3(kBlock), 0, s, sa12, d, G, gcount2));
         LOR_TRY(scan_block_totals(gcount2, G, hdr + 2, s));
-        LOR_LAUNCH(F_NONSAMPLE, (double)d.m * 4 + (double)d.n0 * (8 + sizeof(CH)), s,
+        LOR_LAUNCH("k_ns_write", (double)d.m * 4 + (double)d.n0 * (8 + sizeof(CH)), s,
                    hipLaunchKernelGGL(k_ns_write<CH>, dim3(G), dim3(kBlock), 0, s, t, sa12, d, G, gcount2, keys0,
                                       vals0));
         bool alt;
@@ -627,10 +729,10 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
         const uint32_t *A = alt ? vals1 : vals0;
         const int32_t *B = sa12 + d.dummy;
         const uint32_t nB = d.m - d.dummy;
-        LOR_LAUNCH(F_MERGE_PART, (double)(parts + 1) * 4, s,
+        LOR_LAUNCH("k_merge_partition", (double)(parts + 1) * 4, s,
                    hipLaunchKernelGGL(k_merge_partition<CH>, dim3(div_up(parts + 1, kBlock)), dim3(kBlock), 0, s,
                                       rec, A, d.n0, B, nB, d, parts, split));
-        LOR_LAUNCH(F_MERGE, (double)n * (4 + 4 + sizeof(Rec<CH>)), s,
+        LOR_LAUNCH("k_merge", (double)n * (4 + 4 + sizeof(Rec<CH>)), s,
                    hipLaunchKernelGGL(k_merge<CH>, dim3(parts), dim3(kBlock), 0, s, rec, A, d.n0, B, nB, d, split,
                                       sa));
     }
@@ -663,7 +765,7 @@ __global__ __launch_bounds__(kBlock) void k_zero_words(uint32_t *p, uint32_t cou
 
 lor_status zero_words(uint32_t *p, uint32_t count, hipStream_t s) {
     if (!count) return LOR_OK;
-    LOR_LAUNCH(F_MISC, 4.0 * count, s,
+    LOR_LAUNCH("k_zero_words", 4.0 * count, s,
                hipLaunchKernelGGL(k_zero_words, dim3(grid_for(count)), dim3(kBlock), 0, s, p, count));
     return LOR_OK;
 }
@@ -675,7 +777,7 @@ lor_status join_text(const uint8_t *seqs, const int64_t *offsets, int32_t k, uin
     for (int j = 0; j <= k; ++j) st.start[j] = (int32_t)(offsets[j] + j);
     const uint32_t N = (uint32_t)(offsets[k] + k);
     if (N == 0) return LOR_OK;
-    LOR_LAUNCH(F_JOIN, 2.0 * N, s,
+    LOR_LAUNCH("k_join", 2.0 * N, s,
                hipLaunchKernelGGL(k_join, dim3(grid_for(div_up(N, 4))), dim3(kBlock), 0, s, seqs, st, N, out,
                                   err_word));
     return LOR_OK;

@@ -1,86 +1,130 @@
 // LCP array on gfx950 (Section III, Table IV: LCP[r] = lcp of the suffixes
 // at ranks r-1 and r; the paper cites Kasai et al. for its construction).
 //
-// Permuted-LCP method in three passes:
-//   phi    : Phi[SA[r]] = SA[r-1] (Phi[SA[0]] = -1), optionally ISA[SA[r]] = r;
-//   plcp   : PLCP[i] = lcp(suffix i, suffix Phi[i]) walking the text in
-//            position order, so PLCP[i+1] >= PLCP[i] - 1 (Kasai's bound)
-//            lets each step resume the comparison; the text is cut into
-//            chunks of consecutive positions, one per thread, and each chunk
-//            starts its first comparison from zero. PLCP overwrites Phi.
-//   permute: LCP[r] = PLCP[SA[r]].
+// Permuted-LCP method:
+//   phi    : for every rank r, the pair (r, SA[r-1]) goes to text position
+//            SA[r] -- the inverse permutation and Phi together. The pairs
+//            travel as 64-bit keys (SA[r] << 32 | SA[r-1]) through one radix
+//            pass on the top bits of SA[r], then are stored bucket by bucket
+//            (see scatter.hip for why bucketing beats a random scatter);
+//   plcp   : PLCP[i] = lcp(suffix i, suffix Phi[i]). Kasai's bound
+//            PLCP[i+1] >= PLCP[i] - 1 iterates to PLCP[i+d] >= PLCP[i] - d.
+//            A wave owns a run of 64*K consecutive positions; lane l takes
+//            positions l, l+64, l+128, ... and resumes each comparison from
+//            its previous result minus 64. Loads of neighbouring lanes are
+//            contiguous, and inside long repeats (where the bound pays off)
+//            every lane does the same short extension, so no lane stalls
+//            its wave. The comparison reads 8 symbols at a time. ISA is
+//            written out here, sequentially;
+//   place  : LCP[ISA[i]] = PLCP[i], a bucketed scatter.
 #include "lor_internal.hpp"
 
 namespace lor {
 
 namespace {
 
-constexpr uint32_t kPlcpChunk = 64;   // consecutive text positions per thread
+constexpr uint32_t kPlcpSteps = 128;   // positions per lane; a wave covers 64 * kPlcpSteps
 
-__global__ __launch_bounds__(kBlock) void k_phi(const int32_t *__restrict__ sa, uint32_t n,
-                                                int32_t *__restrict__ phi, int32_t *__restrict__ isa) {
+__global__ __launch_bounds__(kBlock) void k_phi_keys(const int32_t *__restrict__ sa, uint32_t n,
+                                                     uint64_t *__restrict__ keys) {
     for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
-        const int32_t p = sa[r];
-        if ((uint32_t)p >= n) continue;   // not a permutation of 0..n-1: skip
-        phi[p] = r ? sa[r - 1] : -1;
-        if (isa) isa[p] = (int32_t)r;
+        const uint32_t p = (uint32_t)sa[r];
+        const uint32_t prev = r ? (uint32_t)sa[r - 1] : 0xffffffffu;
+        keys[r] = ((uint64_t)(p < n ? p : 0xffffffffu) << 32) | prev;
     }
+}
+
+// isa_phi[SA[r]] = (r, SA[r-1]) from the bucketed (key, r) pairs.
+__global__ __launch_bounds__(kBlock) void k_phi_place(const uint64_t *__restrict__ keys,
+                                                      const uint32_t *__restrict__ ranks, uint32_t n,
+                                                      int2 *__restrict__ isa_phi) {
+    const uint32_t i = dev::xcd_block() * kBlock + threadIdx.x;   // one pair per thread, in bucket order
+    if (i >= n) return;
+    const uint64_t k = keys[i];
+    const uint32_t p = (uint32_t)(k >> 32);
+    if (p < n) isa_phi[p] = make_int2((int32_t)ranks[i], (int32_t)(uint32_t)k);
+}
+
+// 8 text bytes starting at byte offset a; requires a + 16 <= n and an
+// 8-byte aligned text (two aligned loads, then a funnel shift).
+__device__ __forceinline__ uint64_t load8(const uint8_t *__restrict__ t, uint32_t a) {
+    const uint64_t *w = reinterpret_cast<const uint64_t *>(t + (a & ~7u));
+    const uint32_t sh = (a & 7u) * 8u;
+    const uint64_t lo = w[0], hi = w[1];
+    return sh ? (lo >> sh) | (hi << (64u - sh)) : lo;
 }
 
 // Common-prefix length of suffixes i and j, knowing the first h symbols agree.
 __device__ __forceinline__ uint32_t extend(const uint8_t *__restrict__ t, uint32_t n, uint32_t i, uint32_t j,
-                                           uint32_t h) {
+                                           uint32_t h, bool wide) {
     const uint32_t lim = n - max(i, j);   // symbols available in both
+    if (wide) {
+        while (h + 16 <= lim) {
+            const uint64_t x = load8(t, i + h) ^ load8(t, j + h);
+            if (x) return h + (uint32_t)(__builtin_ctzll(x) >> 3);
+            h += 8;
+        }
+    }
     while (h < lim && t[i + h] == t[j + h]) ++h;
     return h;
 }
 
 __global__ __launch_bounds__(kBlock) void k_plcp(const uint8_t *__restrict__ t, uint32_t n,
-                                                 int32_t *__restrict__ phi_plcp) {
-    const uint32_t chunks = (n + kPlcpChunk - 1) / kPlcpChunk;
-    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < chunks; c += gridDim.x * kBlock) {
-        const uint32_t i0 = c * kPlcpChunk, i1 = min(n, i0 + kPlcpChunk);
+                                                 const int2 *__restrict__ isa_phi, int32_t *__restrict__ plcp,
+                                                 int32_t *__restrict__ isa_out, int wide) {
+    constexpr uint32_t span = kWave * kPlcpSteps;
+    const uint32_t waves = (n + span - 1) / span;
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint32_t w = (blockIdx.x * kBlock + threadIdx.x) / kWave; w < waves; w += gridDim.x * (kBlock / kWave)) {
         uint32_t h = 0;
-        for (uint32_t i = i0; i < i1; ++i) {
-            const int32_t j = phi_plcp[i];
+        for (uint32_t k = 0, i = w * span + lane; k < kPlcpSteps && i < n; ++k, i += kWave) {
+            const int2 q = isa_phi[i];
+            isa_out[i] = q.x;
+            const int32_t j = q.y;
             if (j < 0 || (uint32_t)j >= n) {
-                phi_plcp[i] = 0;
+                plcp[i] = 0;
                 h = 0;
                 continue;
             }
-            h = extend(t, n, i, (uint32_t)j, h);
-            phi_plcp[i] = (int32_t)h;
-            h = h ? h - 1 : 0;
+            h = extend(t, n, i, (uint32_t)j, h, wide != 0);
+            plcp[i] = (int32_t)h;
+            h = h > kWave ? h - kWave : 0;
         }
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_permute(const int32_t *__restrict__ sa,
-                                                    const int32_t *__restrict__ plcp, uint32_t n,
-                                                    int32_t *__restrict__ lcp) {
-    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
-        const uint32_t p = (uint32_t)sa[r];
-        lcp[r] = p < n ? plcp[p] : -1;
     }
 }
 
 }  // namespace
 
-size_t lcp_workspace(uint64_t n) { return (size_t)n * 4 + 512; }
+size_t lcp_workspace(uint64_t n) { return (size_t)n * 28 + radix_counts_words(n) * 4 + 4096; }
 
 lor_status lcp_build(const uint8_t *text, uint32_t n, const int32_t *sa, int32_t *lcp, int32_t *isa, Arena &ar,
                      hipStream_t s) {
-    int32_t *phi;
-    LOR_TAKE(ar, int32_t, n, phi);
+    uint64_t *keys, *keys2;       // keys later holds the (ISA, Phi) pairs
+    uint32_t *vals2, *plcp, *isa_tmp, *counts;
+    LOR_TAKE(ar, uint64_t, n, keys);
+    LOR_TAKE(ar, uint64_t, n, keys2);
+    LOR_TAKE(ar, uint32_t, n, vals2);
+    LOR_TAKE(ar, uint32_t, n, plcp);
+    LOR_TAKE(ar, uint32_t, n, isa_tmp);
+    LOR_TAKE(ar, uint32_t, radix_counts_words(n), counts);
     if (n == 0) return LOR_OK;
-    LOR_LAUNCH(F_PHI, (double)n * (isa ? 12 : 8), s,
-               hipLaunchKernelGGL(k_phi, dim3(grid_for(n)), dim3(kBlock), 0, s, sa, n, phi, isa));
-    const uint32_t chunks = div_up(n, kPlcpChunk);
-    LOR_LAUNCH(F_PLCP, (double)n * 11, s,
-               hipLaunchKernelGGL(k_plcp, dim3(grid_for(chunks)), dim3(kBlock), 0, s, text, n, phi));
-    LOR_LAUNCH(F_PERMUTE, (double)n * 12, s,
-               hipLaunchKernelGGL(k_permute, dim3(grid_for(n)), dim3(kBlock), 0, s, sa, phi, n, lcp));
-    return LOR_OK;
+    int2 *isa_phi = reinterpret_cast<int2 *>(keys);
+    int32_t *isa_w = isa ? isa : reinterpret_cast<int32_t *>(isa_tmp);
+    const int wide = ((uintptr_t)text % 8) == 0;
+    int shift, nbits;
+    bucket_digit(n, &shift, &nbits);
+    LOR_LAUNCH("k_phi_keys", (double)n * 12, s,
+               hipLaunchKernelGGL(k_phi_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, sa, n, keys));
+    LOR_TRY(radix_pass<uint64_t>(keys, nullptr, 0, keys2, vals2, n, 32 + shift, nbits, counts, s));
+    LOR_LAUNCH("k_phi_place", (double)n * 20, s,
+               hipLaunchKernelGGL(k_phi_place, dim3(xcd_grid(n)), dim3(kBlock), 0, s, keys2, vals2, n, isa_phi));
+    const uint32_t waves = div_up(n, kWave * kPlcpSteps);
+    LOR_LAUNCH("k_plcp", (double)n * 17, s,
+               hipLaunchKernelGGL(k_plcp, dim3(grid_for((uint64_t)waves * kWave)), dim3(kBlock), 0, s, text, n, isa_phi,
+                                  reinterpret_cast<int32_t *>(plcp), isa_w, wide));
+    uint32_t *tmp_idx = reinterpret_cast<uint32_t *>(keys2);
+    return bucketed_scatter(lcp, n, reinterpret_cast<const uint32_t *>(isa_w), plcp, 0, n, tmp_idx, tmp_idx + n,
+                            counts, s);
 }
 
 }  // namespace lor

@@ -83,19 +83,17 @@ constexpr size_t kHeaderBytes = 256;
 int num_cus();
 
 // -------------------------------------------------------- kernel timing
-enum Family {
-    F_JOIN, F_KEYS, F_RADIX_COUNT, F_RADIX_SCAN, F_RADIX_SCATTER, F_NAME, F_RANK, F_RECORDS,
-    F_NONSAMPLE, F_MERGE_PART, F_MERGE, F_PHI, F_PLCP, F_PERMUTE, F_ST, F_QUERY, F_OVERLAP,
-    F_MISC, F_NUM
-};
+// Timing is keyed by kernel name, so the figures line up with a profiler's.
 bool timing_on();
-int timing_begin(hipStream_t s, Family f, double bytes);
+int timing_begin(hipStream_t s, const char *kernel, double bytes);
 void timing_end(int token, hipStream_t s);
+bool trace_on();   // LOR_TRACE set in the environment: per-level notes on stderr
 
 // Launch helper: records events around the launch when timing is enabled.
-#define LOR_LAUNCH(family, bytes, stream, ...)                                          \
+// `kernel` is the kernel's name; `bytes` its algorithmic bytes for this launch.
+#define LOR_LAUNCH(kernel, bytes, stream, ...)                                          \
     do {                                                                                \
-        int tk_ = ::lor::timing_on() ? ::lor::timing_begin((stream), (family), (bytes)) : -1; \
+        int tk_ = ::lor::timing_on() ? ::lor::timing_begin((stream), (kernel), (bytes)) : -1; \
         __VA_ARGS__;                                                                    \
         LOR_CHECK_LAUNCH();                                                             \
         if (tk_ >= 0) ::lor::timing_end(tk_, (stream));                                 \
@@ -112,6 +110,18 @@ inline uint32_t grid_for(uint64_t items, uint32_t per_block = kBlock) {
     return (uint32_t)g;
 }
 
+// MI355X: 8 XCDs (each with its own L2); workgroups are dealt to them
+// round-robin by workgroup index.
+constexpr uint32_t kXcds = 8;
+
+// Grid of one thread per item for kernels that remap workgroups per XCD:
+// a multiple of kXcds workgroups.
+inline uint32_t xcd_grid(uint64_t items) {
+    uint64_t g = (items + kBlock - 1) / kBlock;
+    g = (g + kXcds - 1) / kXcds * kXcds;
+    return (uint32_t)(g ? g : kXcds);
+}
+
 inline int bits_for(uint64_t maxval) {   // bits needed to hold 0..maxval
     int b = 0;
     while (b < 64 && (maxval >> b) != 0) ++b;
@@ -123,15 +133,36 @@ inline int bits_for(uint64_t maxval) {   // bits needed to hold 0..maxval
 // (k0, v0) hold the input; (k1, v1) are same-sized alternates. On return
 // *in_alt says whether the sorted data ended in (k1, v1).
 size_t radix_counts_words(uint64_t n);
+// One stable pass on digit bits [shift, shift + nbits) (nbits <= 8) from
+// (ki, vi) to (ko, vo); vi == nullptr stands for values e + voff.
+template <typename K>
+lor_status radix_pass(const K *ki, const uint32_t *vi, uint32_t voff, K *ko, uint32_t *vo, uint32_t n, int shift,
+                      int nbits, uint32_t *counts, hipStream_t s);
 template <typename K>
 lor_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, uint32_t n, int bit_lo,
                       int bit_hi, uint32_t *counts, hipStream_t s, bool *in_alt);
 int radix_passes(int bit_lo, int bit_hi);
 
+// ------------------------------------------------------ bucketed scatter
+// dst[idx[i]] = val[i] for i < n (idx a permutation into dst[0..dst_n) or a
+// subset of it): one radix pass partitions the pairs by the top 8 bits of
+// idx, then a second kernel stores them bucket by bucket, so stores to one
+// range of dst are close in time and combine in L2 / the Infinity Cache
+// instead of each costing a line of HBM traffic. val == nullptr stands for
+// values i + voff. tmp_idx/tmp_val: n words each; counts: radix_counts_words.
+lor_status bucketed_scatter(int32_t *dst, uint32_t dst_n, const uint32_t *idx, const uint32_t *val, uint32_t voff,
+                            uint32_t n, uint32_t *tmp_idx, uint32_t *tmp_val, uint32_t *counts, hipStream_t s);
+// Digit (shift, nbits <= 8) that splits 0..dst_n-1 into at most 256 slices.
+void bucket_digit(uint32_t dst_n, int *shift, int *nbits);
+
 // ------------------------------------------------------------- device scan
 // Exclusive scan of `count` u32 block totals in place (one workgroup);
-// writes the grand total to *total.
+// writes the grand total to *total (nullable).
 lor_status scan_block_totals(uint32_t *vals, uint32_t count, uint32_t *total, hipStream_t s);
+// Exclusive scan of `count` words in place across the device (reduce, scan
+// of partials, downsweep). tmp: scan_tmp_words() words.
+constexpr size_t kScanTmpWords = 1024 + 64;
+lor_status scan_exclusive(uint32_t *data, uint32_t count, uint32_t *tmp, uint32_t *total, hipStream_t s);
 
 // ----------------------------------------------------------------- DC3
 // Suffix array of a text with symbols in 1..alphabet (u8 texts are read as
@@ -178,6 +209,13 @@ lor_status overlap_scan(const int32_t *sa, const int32_t *lcp, uint32_t n, const
 // ------------------------------------------------------- device helpers
 namespace lor {
 namespace dev {
+
+// Workgroup b is placed on XCD b mod kXcds; this maps it to the
+// (b mod kXcds)-th contiguous share of a one-thread-per-item grid.
+__device__ __forceinline__ uint32_t xcd_block() {
+    const uint32_t per = gridDim.x / kXcds;
+    return (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+}
 
 __device__ __forceinline__ unsigned lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));

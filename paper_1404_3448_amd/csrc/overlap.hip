@@ -3,7 +3,7 @@
 // positions).
 //
 // Pass 1 (max): L = largest LCP[r] over ranks whose two suffixes start in
-//   different sequences; a per-thread chunk scan, a workgroup reduction and
+//   different sequences; coalesced per-rank loads, a workgroup reduction and
 //   one atomicMax per workgroup (max is order-independent, so deterministic).
 // Pass 2 (positions): the suffixes sharing one L-symbol prefix form a maximal
 //   run of ranks whose LCP is >= L. The reported pair is the lexicographically
@@ -14,8 +14,10 @@
 //   s1. Merging two summaries keeps this exact, so chunks of ranks are
 //   summarised independently (head = part of a run begun earlier, tail =
 //   last open run, best = best pair of the runs closed inside) and combined
-//   in rank order by an associative rule: a workgroup tree, then one
-//   workgroup over the workgroup results.
+//   in rank order by an associative rule: a workgroup tree per tile, tiles
+//   in order inside a workgroup, then one workgroup over the workgroup
+//   results. A tile where no LCP reaches L holds only one-suffix runs; its
+//   summary needs the last suffix alone, so such tiles read only LCP.
 #include <climits>
 
 #include "lor_internal.hpp"
@@ -24,8 +26,10 @@ namespace lor {
 
 namespace {
 
-constexpr uint32_t kChunk = 32;                       // ranks per thread
-constexpr uint32_t kGroupRanks = kChunk * kBlock;
+constexpr uint32_t kChunk = 16;                       // ranks per thread in a tile
+constexpr uint32_t kTileRanks = kChunk * kBlock;      // 4096 ranks per tile
+constexpr uint32_t kTilesPerGroup = 16;
+constexpr uint32_t kGroupRanks = kTileRanks * kTilesPerGroup;
 
 struct RunSum {
     int32_t m1, s1, m2, s2;
@@ -112,15 +116,9 @@ __global__ __launch_bounds__(kBlock) void k_cross_max(const int32_t *__restrict_
     for (int i = threadIdx.x; i <= st.k; i += kBlock) s_start[i] = st.start[i];
     __syncthreads();
     int32_t best = 0;
-    const uint32_t chunks = (n + kChunk - 1) / kChunk;
-    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < chunks; c += gridDim.x * kBlock) {
-        const uint32_t r0 = c * kChunk, r1 = min(n, r0 + kChunk);
-        int32_t prev = r0 ? seq_of(s_start, st.k, sa[r0 - 1]) : -1;
-        for (uint32_t r = r0; r < r1; ++r) {
-            const int32_t cur = seq_of(s_start, st.k, sa[r]);
-            if (r > 0 && cur != prev) best = max(best, lcp[r]);
-            prev = cur;
-        }
+    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x + 1; r < n; r += gridDim.x * kBlock) {
+        const int32_t v = lcp[r];
+        if (v > best && seq_of(s_start, st.k, sa[r - 1]) != seq_of(s_start, st.k, sa[r])) best = v;
     }
     for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o, 64));
     if ((threadIdx.x & 63u) == 0) s_red[threadIdx.x >> 6] = best;
@@ -146,27 +144,64 @@ __global__ __launch_bounds__(kBlock) void k_runs(const int32_t *__restrict__ sa,
                                                  ChunkSum *__restrict__ out) {
     __shared__ int32_t s_start[kMaxSeqs + 1];
     __shared__ ChunkSum s_sum[kBlock];
+    __shared__ int32_t s_sa[kTileRanks];
+    __shared__ int32_t s_lcp[kTileRanks];
     for (int i = threadIdx.x; i <= st.k; i += kBlock) s_start[i] = st.start[i];
     __syncthreads();
     const int32_t L = (int32_t)*Lp;
-    const uint32_t r0 = blockIdx.x * kGroupRanks + threadIdx.x * kChunk;
-    const uint32_t r1 = min(n, r0 + kChunk);
-    ChunkSum c = chunk_empty();
-    for (uint32_t r = r0; r < r1; ++r) {
-        const int32_t p = sa[r];
-        const RunSum e{p, seq_of(s_start, st.k, p), INT_MAX, -1};
-        if (r == 0 || lcp[r] < L) {           // r starts a run
-            if (c.has_b) finalize(c.tail, c.bp, c.bq);
-            c.has_b = 1;
-            c.tail = e;
-        } else if (c.has_b) {
-            c.tail = run_merge(c.tail, e);
-        } else {
-            c.head = run_merge(c.head, e);
+    ChunkSum total = chunk_empty();                 // meaningful in thread 0
+    const uint32_t tiles = (n + kTileRanks - 1) / kTileRanks;
+    const uint32_t t0 = blockIdx.x * kTilesPerGroup, t1 = min(tiles, t0 + kTilesPerGroup);
+    for (uint32_t t = t0; t < t1; ++t) {
+        const uint32_t base = t * kTileRanks;
+        const uint32_t cnt = min(kTileRanks, n - base);
+        int any = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < kChunk; ++i) {
+            const uint32_t j = i * kBlock + threadIdx.x;
+            const int32_t v = j < cnt ? lcp[base + j] : 0;
+            if (j < cnt) s_lcp[j] = v;
+            any |= (base + j != 0) && j < cnt && v >= L;
         }
+        any = __syncthreads_or(any);
+        if (!any) {
+            // every rank starts a run; only the last run can continue
+            if (threadIdx.x == 0) {
+                const int32_t p = sa[base + cnt - 1];
+                ChunkSum c = chunk_empty();
+                c.has_b = 1;
+                c.tail = RunSum{p, seq_of(s_start, st.k, p), INT_MAX, -1};
+                total = chunk_combine(total, c);
+            }
+            __syncthreads();
+            continue;
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < kChunk; ++i) {
+            const uint32_t j = i * kBlock + threadIdx.x;
+            if (j < cnt) s_sa[j] = sa[base + j];
+        }
+        __syncthreads();
+        ChunkSum c = chunk_empty();
+        const uint32_t j0 = threadIdx.x * kChunk;
+        for (uint32_t j = j0; j < min(cnt, j0 + kChunk); ++j) {
+            const int32_t p = s_sa[j];
+            const RunSum e{p, seq_of(s_start, st.k, p), INT_MAX, -1};
+            if (base + j == 0 || s_lcp[j] < L) {    // starts a run
+                if (c.has_b) finalize(c.tail, c.bp, c.bq);
+                c.has_b = 1;
+                c.tail = e;
+            } else if (c.has_b) {
+                c.tail = run_merge(c.tail, e);
+            } else {
+                c.head = run_merge(c.head, e);
+            }
+        }
+        block_reduce_chunks(s_sum, c);
+        if (threadIdx.x == 0) total = chunk_combine(total, s_sum[0]);
+        __syncthreads();
     }
-    block_reduce_chunks(s_sum, c);
-    if (threadIdx.x == 0) out[blockIdx.x] = s_sum[0];
+    if (threadIdx.x == 0) out[blockIdx.x] = total;
 }
 
 __global__ __launch_bounds__(kBlock) void k_runs_final(const ChunkSum *__restrict__ in, uint32_t count,
@@ -202,17 +237,16 @@ lor_status overlap_scan(const int32_t *sa, const int32_t *lcp, uint32_t n, const
     for (int x = 0; x < 5; ++x) result[x] = -1;
     result[0] = 0;
     if (n < 2) return LOR_OK;
-    LOR_LAUNCH(F_MISC, 0, s, hipLaunchKernelGGL(k_init, dim3(1), dim3(kBlock), 0, s, words, 4));
-    const uint32_t chunks = div_up(n, kChunk);
-    LOR_LAUNCH(F_OVERLAP, (double)n * 8, s,
-               hipLaunchKernelGGL(k_cross_max, dim3(grid_for(chunks)), dim3(kBlock), 0, s, sa, lcp, n, st, words));
+    LOR_LAUNCH("k_init", 0, s, hipLaunchKernelGGL(k_init, dim3(1), dim3(kBlock), 0, s, words, 4));
+    LOR_LAUNCH("k_cross_max", (double)n * 8, s,
+               hipLaunchKernelGGL(k_cross_max, dim3(grid_for(n)), dim3(kBlock), 0, s, sa, lcp, n, st, words));
     uint32_t L = 0;
     LOR_HIP(hipMemcpyAsync(&L, words, 4, hipMemcpyDeviceToHost, s));
     LOR_HIP(hipStreamSynchronize(s));
     if (L == 0) return LOR_OK;
-    LOR_LAUNCH(F_OVERLAP, (double)n * 8, s,
+    LOR_LAUNCH("k_runs", (double)n * 4, s,
                hipLaunchKernelGGL(k_runs, dim3(groups), dim3(kBlock), 0, s, sa, lcp, n, st, words, sums));
-    LOR_LAUNCH(F_OVERLAP, (double)groups * sizeof(ChunkSum), s,
+    LOR_LAUNCH("k_runs_final", (double)groups * sizeof(ChunkSum), s,
                hipLaunchKernelGGL(k_runs_final, dim3(1), dim3(kBlock), 0, s, sums, groups, words + 1));
     uint32_t pq[2];
     LOR_HIP(hipMemcpyAsync(pq, words + 1, 8, hipMemcpyDeviceToHost, s));

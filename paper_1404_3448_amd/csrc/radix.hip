@@ -6,8 +6,9 @@
 // Here a pass handles an 8-bit digit and runs as three kernels:
 //   1. count  : every workgroup owns a contiguous run of tiles and builds the
 //               digit histogram of its run in LDS (per-wave sub-histograms);
-//   2. scan   : one workgroup turns the digit-major table counts[d][g] into
-//               exclusive global offsets;
+//   2. scan   : a device-wide exclusive scan turns the digit-major table
+//               counts[d][g] into global offsets (digit d of group g starts
+//               after every smaller digit and after digit d of groups < g);
 //   3. scatter: every workgroup walks its tiles in order; inside a tile each
 //               wave ranks its elements by digit with 8 ballots per round
 //               (lanes with the same digit form a peer mask; the rank is the
@@ -69,6 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_count(const K *__restrict__ ke
     counts[(size_t)tid * groups + blockIdx.x] = s;
 }
 
+// vin == nullptr: the value of input element e is e + voff.
 template <typename K, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(const K *__restrict__ kin,
                                                           const uint32_t *__restrict__ vin,
@@ -76,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const K *__restrict__ 
                                                           uint32_t *__restrict__ vout, uint32_t n,
                                                           uint32_t tiles, uint32_t groups, int shift,
                                                           int nbits,
-                                                          const uint32_t *__restrict__ offs) {
+                                                          const uint32_t *__restrict__ offs, uint32_t voff) {
     constexpr uint32_t TILE = kBlock * ITEMS;
     constexpr int W = kBlock / kWave;
     __shared__ uint32_t s_cnt[W][kBins];   // per-wave digit counters, then digit bases per wave
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const K *__restrict__ 
             uint32_t e = wfirst + r * kWave;
             bool ok = e < n;
             k[r] = ok ? kin[e] : K(0);
-            v[r] = ok ? vin[e] : 0u;
+            v[r] = ok ? (vin ? vin[e] : e + voff) : 0u;
         }
 #pragma unroll
         for (int r = 0; r < ITEMS; ++r) {
@@ -192,6 +194,57 @@ __global__ __launch_bounds__(1024) void k_scan_inplace(uint32_t *__restrict__ va
     if (tid == 0 && total) *total = tot;
 }
 
+// Device-wide exclusive scan: per-group sums of contiguous ranges, a scan of
+// the sums, then each group rescans its range from its base.
+constexpr int kScanItems = 8;
+constexpr uint32_t kScanTile = kBlock * kScanItems;
+constexpr uint32_t kScanGroups = 1024;
+
+__device__ __forceinline__ void scan_range(uint32_t count, uint32_t groups, uint32_t g, uint32_t *b,
+                                           uint32_t *e) {
+    const uint32_t tiles = (count + kScanTile - 1) / kScanTile;
+    *b = min(count, (uint32_t)((uint64_t)tiles * g / groups) * kScanTile);
+    *e = min(count, (uint32_t)((uint64_t)tiles * (g + 1) / groups) * kScanTile);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *__restrict__ data, uint32_t count,
+                                                        uint32_t groups, uint32_t *__restrict__ sums) {
+    __shared__ uint32_t s_tmp[kBlock / kWave];
+    uint32_t b, e;
+    scan_range(count, groups, blockIdx.x, &b, &e);
+    uint32_t acc = 0;
+    for (uint32_t i = b + threadIdx.x; i < e; i += kBlock) acc += data[i];
+    uint32_t tot;
+    dev::block_exclusive_sum(acc, s_tmp, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t *__restrict__ data, uint32_t count, uint32_t groups,
+                                                      const uint32_t *__restrict__ sums) {
+    __shared__ uint32_t s_tmp[kBlock / kWave];
+    uint32_t b, e;
+    scan_range(count, groups, blockIdx.x, &b, &e);
+    uint32_t base = sums[blockIdx.x];
+    for (uint32_t t0 = b; t0 < e; t0 += kScanTile) {
+        const uint32_t i0 = t0 + threadIdx.x * kScanItems;
+        uint32_t v[kScanItems];
+        uint32_t c = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            v[i] = (i0 + i < e) ? data[i0 + i] : 0u;
+            c += v[i];
+        }
+        uint32_t tot;
+        uint32_t run = base + dev::block_exclusive_sum(c, s_tmp, &tot);
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            if (i0 + i < e) data[i0 + i] = run;
+            run += v[i];
+        }
+        base += tot;
+    }
+}
+
 template <typename K>
 uint32_t groups_for(uint32_t n, uint32_t *tiles) {
     constexpr uint32_t TILE = kBlock * RadixCfg<K>::kItems;
@@ -201,44 +254,70 @@ uint32_t groups_for(uint32_t n, uint32_t *tiles) {
 
 }  // namespace
 
-size_t radix_counts_words(uint64_t) { return (size_t)kBins * kMaxGroups + 64; }
+size_t radix_counts_words(uint64_t) { return (size_t)kBins * kMaxGroups + kScanTmpWords + 64; }
+
+lor_status scan_exclusive(uint32_t *data, uint32_t count, uint32_t *tmp, uint32_t *total, hipStream_t s) {
+    if (count == 0) return LOR_OK;
+    uint32_t tiles = div_up(count, kScanTile);
+    const uint32_t groups = tiles < kScanGroups ? tiles : kScanGroups;
+    if (groups == 1) return scan_block_totals(data, count, total, s);
+    LOR_LAUNCH("k_scan_reduce", 4.0 * count, s,
+               hipLaunchKernelGGL(k_scan_reduce, dim3(groups), dim3(kBlock), 0, s, data, count, groups, tmp));
+    LOR_TRY(scan_block_totals(tmp, groups, total, s));
+    LOR_LAUNCH("k_scan_down", 8.0 * count, s,
+               hipLaunchKernelGGL(k_scan_down, dim3(groups), dim3(kBlock), 0, s, data, count, groups, tmp));
+    return LOR_OK;
+}
 
 int radix_passes(int bit_lo, int bit_hi) {
     return bit_hi > bit_lo ? (bit_hi - bit_lo + kDigitBits - 1) / kDigitBits : 0;
 }
 
 lor_status scan_block_totals(uint32_t *vals, uint32_t count, uint32_t *total, hipStream_t s) {
-    LOR_LAUNCH(F_RADIX_SCAN, 8.0 * count, s,
+    LOR_LAUNCH("k_scan_inplace", 8.0 * count, s,
                hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, vals, count, total));
+    return LOR_OK;
+}
+
+template <typename K>
+lor_status radix_pass(const K *ki, const uint32_t *vi, uint32_t voff, K *ko, uint32_t *vo, uint32_t n, int shift,
+                      int nbits, uint32_t *counts, hipStream_t s) {
+    constexpr int ITEMS = RadixCfg<K>::kItems;
+    if (n == 0) return LOR_OK;
+    uint32_t tiles;
+    const uint32_t groups = groups_for<K>(n, &tiles);
+    const uint32_t mask = (1u << nbits) - 1u;
+    LOR_LAUNCH("k_radix_count", (double)n * sizeof(K), s,
+               hipLaunchKernelGGL((k_radix_count<K, ITEMS>), dim3(groups), dim3(kBlock), 0, s, ki, n, tiles, groups,
+                                  shift, mask, counts));
+    LOR_TRY(scan_exclusive(counts, (uint32_t)kBins * groups, counts + (size_t)kBins * kMaxGroups, nullptr, s));
+    LOR_LAUNCH("k_radix_scatter", (double)n * ((vi ? 2.0 : 1.0) * (sizeof(K) + 4) + (vi ? 0.0 : sizeof(K))), s,
+               hipLaunchKernelGGL((k_radix_scatter<K, ITEMS>), dim3(groups), dim3(kBlock), 0, s, ki, vi, ko, vo, n,
+                                  tiles, groups, shift, nbits, counts, voff));
     return LOR_OK;
 }
 
 template <typename K>
 lor_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, uint32_t n, int bit_lo, int bit_hi,
                       uint32_t *counts, hipStream_t s, bool *in_alt) {
-    constexpr int ITEMS = RadixCfg<K>::kItems;
     *in_alt = false;
     if (n <= 1 || bit_hi <= bit_lo) return LOR_OK;
-    uint32_t tiles;
-    const uint32_t groups = groups_for<K>(n, &tiles);
     K *ki = k0, *ko = k1;
     uint32_t *vi = v0, *vo = v1;
     for (int shift = bit_lo; shift < bit_hi; shift += kDigitBits) {
         const int nbits = min(kDigitBits, bit_hi - shift);
-        const uint32_t mask = (1u << nbits) - 1u;
-        LOR_LAUNCH(F_RADIX_COUNT, (double)n * sizeof(K), s,
-                   hipLaunchKernelGGL((k_radix_count<K, ITEMS>), dim3(groups), dim3(kBlock), 0, s, ki, n,
-                                      tiles, groups, shift, mask, counts));
-        LOR_TRY(scan_block_totals(counts, (uint32_t)kBins * groups, nullptr, s));
-        LOR_LAUNCH(F_RADIX_SCATTER, (double)n * 2.0 * (sizeof(K) + 4), s,
-                   hipLaunchKernelGGL((k_radix_scatter<K, ITEMS>), dim3(groups), dim3(kBlock), 0, s, ki,
-                                      vi, ko, vo, n, tiles, groups, shift, nbits, counts));
+        LOR_TRY(radix_pass<K>(ki, vi, 0, ko, vo, n, shift, nbits, counts, s));
         K *tk = ki; ki = ko; ko = tk;
         uint32_t *tv = vi; vi = vo; vo = tv;
         *in_alt = !*in_alt;
     }
     return LOR_OK;
 }
+
+template lor_status radix_pass<uint32_t>(const uint32_t *, const uint32_t *, uint32_t, uint32_t *, uint32_t *, uint32_t,
+                                         int, int, uint32_t *, hipStream_t);
+template lor_status radix_pass<uint64_t>(const uint64_t *, const uint32_t *, uint32_t, uint64_t *, uint32_t *, uint32_t,
+                                         int, int, uint32_t *, hipStream_t);
 
 template lor_status radix_sort<uint32_t>(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, int, int,
                                          uint32_t *, hipStream_t, bool *);

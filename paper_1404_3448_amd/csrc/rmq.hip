@@ -94,7 +94,7 @@ lor_status rmq_build_levels(const int32_t *lcp, uint32_t n, int32_t *table, int 
         int32_t *cur = table + rmq_level_offset(n, k);
         const uint32_t half = 1u << (k - 1);
         const uint32_t cnt = n - (1u << k) + 1u;
-        LOR_LAUNCH(F_ST, (double)cnt * 8, s,
+        LOR_LAUNCH("k_st_level", (double)cnt * 8, s,
                    hipLaunchKernelGGL(k_st_level, dim3(grid_for(cnt)), dim3(kBlock), 0, s, prev, half, cnt, cur));
     }
     return LOR_OK;
@@ -105,7 +105,7 @@ lor_status rmq_queries(const int32_t *table, uint32_t n, int levels, const int32
                        int32_t *argmin_out, hipStream_t s) {
     if (nq == 0) return LOR_OK;
     Levels L{lcp, table, n, levels};
-    LOR_LAUNCH(F_QUERY, (double)nq * (mode ? 28 : 20), s,
+    LOR_LAUNCH("k_query", (double)nq * (mode ? 28 : 20), s,
                hipLaunchKernelGGL(k_query, dim3(grid_for(nq)), dim3(kBlock), 0, s, L, isa, mode, qi, qj, nq,
                                   min_out, argmin_out));
     return LOR_OK;
