@@ -286,3 +286,42 @@ def test_noncoding_pair_8m():
     assert np.array_equal(host(r["sa"]), want_sa)
     assert np.array_equal(host(r["lcp"]), want_lcp)
     assert r["overlap"] == oracle.overlap(want_sa, want_lcp, w.offsets)
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_long_text_1g_full_size():
+    """The 1G-base workload (16 x 2^26 bases, 10M queries) at full size, in the
+    benchmark's launch configuration. SA and LCP are certified by the oracle's
+    certificate (permutation + strict adjacent order + exact LCP, which proves
+    them equal to the oracle's definition); ISA is checked as the inverse of SA;
+    the overlap equals the oracle's scan of the certified arrays; 20,000 sampled
+    suffix-pair queries equal direct character comparison."""
+    w = synth.long_text()
+    n = w.joined_length
+    say("1G generated", n)
+    seqs = dev(w.concat)
+    joined = torch.empty(n, dtype=torch.uint8, device=DEV)
+    sa = torch.empty(n, dtype=torch.int32, device=DEV)
+    lcp = torch.empty(n, dtype=torch.int32, device=DEV)
+    isa = torch.empty(n, dtype=torch.int32, device=DEV)
+    lor.lor_build_sa(seqs, w.offsets, joined_out=joined, sa_out=sa)
+    lor.lor_build_lcp(joined, sa, lcp_out=lcp, isa_out=isa)
+    rmq = lor.lor_rmq_build(lcp)
+    qi, qj = dev(w.queries[0]), dev(w.queries[1])
+    got, _ = lor.lor_rmq_query(rmq, lcp, isa, 1, qi, qj)
+    ov = lor.lor_longest_overlap(sa, lcp, w.offsets)
+    got_h = host(got)
+    del rmq, qi, qj, got, seqs
+    joined_h, sa_h, lcp_h, isa_h = host(joined), host(sa), host(lcp), host(isa)
+    del joined, sa, lcp, isa
+    torch.cuda.empty_cache()
+    say("1G GPU path done, certifying on the host")
+    assert np.array_equal(joined_h, oracle.join(w.concat, w.offsets))
+    assert oracle.certify(joined_h, sa_h, lcp_h) == -1
+    assert np.array_equal(isa_h[sa_h], np.arange(n, dtype=np.int32))
+    assert ov == oracle.overlap(sa_h, lcp_h, w.offsets)
+    rng = np.random.default_rng(33)
+    pick = rng.choice(w.queries[0].size, size=20000, replace=False)
+    want = oracle.pair_queries(joined_h, w.queries[0][pick], w.queries[1][pick])
+    assert np.array_equal(got_h[pick], want)
