@@ -167,6 +167,23 @@ lor_status lor_longest_overlap(const int32_t *sa, const int32_t *lcp, int64_t n,
                                const int64_t *offsets, int32_t num_seqs,
                                lor_overlap *out_host, void *ws, size_t ws_bytes, void *hip_stream);
 
+/* ------------------------------------------------- batched longest overlap
+ * The longest overlap region (as lor_longest_overlap) of every pair in a
+ * batch of independent sequence pairs, from one DC3 run over all pairs.
+ * seqs: device uint8 bases (0..3) of all sequences concatenated without
+ * separators; offsets: HOST int64[2 * num_pairs + 1], pair p being sequences
+ * 2p (A) and 2p+1 (B), offsets[0] = 0 and non-decreasing; empty sequences
+ * are allowed. 1 <= num_pairs <= 8191 and sum of (|A_p| + |B_p| + 2) must
+ * not exceed 2^31 - 1. out_device: device lor_overlap[num_pairs]; record p
+ * has seq_p/seq_q in {0 (A), 1 (B)} and offsets inside those sequences, and
+ * equals what lor_longest_overlap reports for the pair alone (length 0 gives
+ * -1 for the rest). plan: reserved, must be NULL. A base outside 0..3
+ * returns LOR_EALPHABET. Synchronises hip_stream before returning. */
+size_t lor_longest_overlap_batched_workspace(int64_t total_bases, int32_t num_pairs);
+lor_status lor_longest_overlap_batched(const uint8_t *seqs, const int64_t *offsets, int32_t num_pairs,
+                                       const void *plan, lor_overlap *out_device,
+                                       void *ws, size_t ws_bytes, void *hip_stream);
+
 /* ------------------------------------------------------------ radix sort
  * Stable LSD radix sort of (key, value) pairs by key bits [bit_lo, bit_hi)
  * (Section IV: radix sort from the least to the most significant digit, the

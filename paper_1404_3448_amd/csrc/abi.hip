@@ -371,6 +371,47 @@ lor_status lor_longest_overlap(const int32_t *sa, const int32_t *lcp, int64_t n,
     return LOR_OK;
 }
 
+size_t lor_longest_overlap_batched_workspace(int64_t total_bases, int32_t num_pairs) {
+    if (total_bases < 0 || num_pairs < 1 || num_pairs > (int32_t)kMaxPairs ||
+        total_bases + 2ll * num_pairs > INT32_MAX)
+        return 0;
+    return batch_workspace((uint64_t)total_bases, (uint32_t)num_pairs);
+}
+
+lor_status lor_longest_overlap_batched(const uint8_t *seqs, const int64_t *offsets, int32_t num_pairs,
+                                       const void *plan, lor_overlap *out_device, void *ws, size_t ws_bytes,
+                                       void *hip_stream) {
+    if (num_pairs < 1 || num_pairs > (int32_t)kMaxPairs) {
+        set_error("num_pairs %d outside 1..%u", num_pairs, kMaxPairs);
+        return LOR_EINVAL;
+    }
+    if (!offsets || !out_device || plan) {
+        set_error("NULL offsets/out_device, or a non-NULL plan");
+        return LOR_EINVAL;
+    }
+    if (offsets[0] != 0) {
+        set_error("offsets[0] must be 0");
+        return LOR_EINVAL;
+    }
+    for (int64_t j = 0; j < 2ll * num_pairs; ++j) {
+        if (offsets[j + 1] < offsets[j]) {
+            set_error("offsets decrease at %lld", (long long)j);
+            return LOR_EINVAL;
+        }
+    }
+    const int64_t total = offsets[2ll * num_pairs];
+    if (total + 2ll * num_pairs > INT32_MAX) {
+        set_error("batched joined length exceeds 2^31-1");
+        return LOR_ETOOLARGE;
+    }
+    if (total > 0 && !seqs) {
+        set_error("seqs is NULL");
+        return LOR_EINVAL;
+    }
+    LOR_TRY(check_ws(ws, ws_bytes, lor_longest_overlap_batched_workspace(total, num_pairs)));
+    return batch_overlap(seqs, offsets, (uint32_t)num_pairs, out_device, ws, ws_bytes, (hipStream_t)hip_stream);
+}
+
 size_t lor_sort_pairs_workspace(int64_t n, int32_t key_bytes) {
     if (n < 0 || n > INT32_MAX || (key_bytes != 4 && key_bytes != 8)) return 0;
     return kHeaderBytes + 1024 + (size_t)n * (size_t)(key_bytes + 4) + radix_counts_words((uint64_t)n) * 4;

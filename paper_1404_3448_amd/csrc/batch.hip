@@ -1,0 +1,394 @@
+// Batched longest overlap for many independent sequence pairs on gfx950.
+//
+// All pairs go through one DC3 run. Pair p is written as the tagged text
+//   8p+c(A_p) ... 8p+5  8p+c(B_p) ... 8p+6      (c(base) = base + 1)
+// with 16-bit symbols. The pair tag is the most significant part of every
+// symbol and each pair ends with its own unique separator, so comparing two
+// suffixes of one pair never reads past that separator, and suffixes of
+// different pairs are ordered by pair. The suffix array of the tagged text
+// is therefore the concatenation of every pair's own suffix array, and pair
+// p's suffixes hold exactly the ranks [start_p, start_p + |pair p|) -- the
+// same range as its positions. LCP over 16-bit symbols is 0 between pairs.
+// The overlap scan then runs per pair inside its rank range: one pass for
+// every pair's largest cross-sequence LCP (atomicMax per pair), one pass over
+// the runs of suffixes sharing that many symbols, where every closed run
+// offers (smallest position, smallest position of the other sequence) to its
+// pair with an atomicMin on the packed pair of positions -- a minimum does not
+// depend on the order of arrival, so the result is deterministic.
+#include <algorithm>
+#include <climits>
+#include <vector>
+
+#include "lor_internal.hpp"
+
+namespace lor {
+
+namespace {
+
+constexpr uint32_t kChunk = 16;                        // ranks per thread in a tile
+constexpr uint32_t kTileRanks = kChunk * kBlock;
+constexpr uint32_t kTilesPerGroup = 16;
+constexpr uint32_t kGroupRanks = kTileRanks * kTilesPerGroup;
+
+// Largest j with start[j] <= x over j in [0, count).
+__device__ __forceinline__ uint32_t find_pair(const int32_t *__restrict__ start, uint32_t count, uint32_t x) {
+    uint32_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if ((uint32_t)start[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// start[p] = joined start of pair p (start[P] = N); alen[p] = |A_p|;
+// src[2p], src[2p+1] = offsets of A_p and B_p in the separator-free input.
+__global__ __launch_bounds__(kBlock) void k_join_pairs(const uint8_t *__restrict__ seqs,
+                                                       const int32_t *__restrict__ start,
+                                                       const int32_t *__restrict__ alen,
+                                                       const int64_t *__restrict__ src, uint32_t P, uint32_t N,
+                                                       uint16_t *__restrict__ out, uint32_t *__restrict__ err) {
+    uint32_t bad = 0;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+        const uint32_t p = find_pair(start, P, i);
+        const uint32_t o = i - (uint32_t)start[p];
+        const uint32_t a = (uint32_t)alen[p];
+        const uint32_t plen = (uint32_t)start[p + 1] - (uint32_t)start[p];
+        uint32_t code;
+        if (o < a) {
+            code = seqs[src[2 * p] + o];
+            bad |= code > 3u;
+            code += 1u;
+        } else if (o == a) {
+            code = 5u;
+        } else if (o + 1 < plen) {
+            code = seqs[src[2 * p + 1] + (o - a - 1)];
+            bad |= code > 3u;
+            code += 1u;
+        } else {
+            code = 6u;
+        }
+        out[i] = (uint16_t)(8u * p + code);
+    }
+    if (__any(bad) && dev::lane_id() == 0) atomicOr(err, 1u);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pair_init(uint32_t P, uint32_t *__restrict__ lmax,
+                                                      unsigned long long *__restrict__ best) {
+    for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < P; p += gridDim.x * kBlock) {
+        lmax[p] = 0;
+        best[p] = ~0ull;
+    }
+}
+
+// Is joined position x (inside pair p) in the pair's second sequence?
+__device__ __forceinline__ bool in_b(const int32_t *start, const int32_t *alen, uint32_t p, uint32_t x) {
+    return x > (uint32_t)start[p] + (uint32_t)alen[p];
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_max(const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp,
+                                                    uint32_t n, const int32_t *__restrict__ start,
+                                                    const int32_t *__restrict__ alen, uint32_t P,
+                                                    uint32_t *__restrict__ lmax) {
+    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+        const uint32_t r = base + threadIdx.x;
+        uint32_t p = 0, v = 0;
+        if (r < n) {
+            p = find_pair(start, P, r);
+            if (r > (uint32_t)start[p]) {
+                const int32_t l = lcp[r];
+                if (l > 0 && in_b(start, alen, p, (uint32_t)sa[r - 1]) != in_b(start, alen, p, (uint32_t)sa[r]))
+                    v = (uint32_t)l;
+            }
+        }
+        // one atomic per wave when the wave lies inside one pair
+        const uint32_t p0 = __shfl(p, 0, 64);
+        if (__all(r >= n || p == p0)) {
+            uint32_t m = v;
+            for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+            if (dev::lane_id() == 0 && m > 0) atomicMax(&lmax[p0], m);
+        } else if (v > 0) {
+            atomicMax(&lmax[p], v);
+        }
+    }
+}
+
+struct RunSum {
+    int32_t m1, s1, m2, s2;
+};
+struct ChunkSum {
+    RunSum head, tail;
+    int32_t has_b, pad0, pad1, pad2;
+};
+
+__device__ __forceinline__ RunSum run_empty() { return RunSum{INT_MAX, -1, INT_MAX, -1}; }
+
+__device__ __forceinline__ RunSum run_merge(const RunSum &x, const RunSum &y) {
+    const bool xf = x.m1 <= y.m1;
+    const RunSum &f = xf ? x : y;
+    const RunSum &o = xf ? y : x;
+    RunSum r{f.m1, f.s1, f.m2, f.s2};
+    if (o.m1 != INT_MAX && o.s1 != f.s1 && o.m1 < r.m2) { r.m2 = o.m1; r.s2 = o.s1; }
+    if (o.m2 != INT_MAX && o.s2 != f.s1 && o.m2 < r.m2) { r.m2 = o.m2; r.s2 = o.s2; }
+    return r;
+}
+
+// A closed run offers its pair of positions to the run's pair.
+__device__ __forceinline__ void finalize(const RunSum &r, const int32_t *start, uint32_t P,
+                                         unsigned long long *best) {
+    if (r.m1 == INT_MAX || r.m2 == INT_MAX) return;
+    const uint32_t p = find_pair(start, P, (uint32_t)r.m1);
+    atomicMin(&best[p], ((unsigned long long)(uint32_t)r.m1 << 32) | (uint32_t)r.m2);
+}
+
+__device__ __forceinline__ ChunkSum chunk_empty() {
+    ChunkSum c;
+    c.head = run_empty();
+    c.tail = run_empty();
+    c.has_b = 0;
+    c.pad0 = c.pad1 = c.pad2 = 0;
+    return c;
+}
+
+__device__ __forceinline__ ChunkSum chunk_combine(const ChunkSum &x, const ChunkSum &y, const int32_t *start,
+                                                  uint32_t P, unsigned long long *best) {
+    ChunkSum r = chunk_empty();
+    if (!x.has_b) {
+        r.head = run_merge(x.head, y.head);
+        r.has_b = y.has_b;
+        r.tail = y.tail;
+    } else {
+        r.head = x.head;
+        r.has_b = 1;
+        if (y.has_b) {
+            finalize(run_merge(x.tail, y.head), start, P, best);
+            r.tail = y.tail;
+        } else {
+            r.tail = run_merge(x.tail, y.head);
+        }
+    }
+    return r;
+}
+
+// Rank r starts a run unless it shares at least its pair's L symbols with r-1.
+__device__ __forceinline__ bool run_start(uint32_t r, int32_t l, const int32_t *start, uint32_t P,
+                                          const uint32_t *lmax, uint32_t *pair_out) {
+    const uint32_t p = find_pair(start, P, r);
+    *pair_out = p;
+    const uint32_t L = lmax[p];
+    return r == (uint32_t)start[p] || L == 0 || (uint32_t)l < L;
+}
+
+__device__ void reduce_chunks(ChunkSum *s, ChunkSum mine, const int32_t *start, uint32_t P,
+                              unsigned long long *best) {
+    s[threadIdx.x] = mine;
+    __syncthreads();
+    for (unsigned stride = 1; stride < kBlock; stride <<= 1) {
+        if ((threadIdx.x & (2 * stride - 1)) == 0)
+            s[threadIdx.x] = chunk_combine(s[threadIdx.x], s[threadIdx.x + stride], start, P, best);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_runs(const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp,
+                                                     uint32_t n, const int32_t *__restrict__ start,
+                                                     const int32_t *__restrict__ alen, uint32_t P,
+                                                     const uint32_t *__restrict__ lmax,
+                                                     unsigned long long *__restrict__ best,
+                                                     ChunkSum *__restrict__ out) {
+    __shared__ ChunkSum s_sum[kBlock];
+    __shared__ int32_t s_sa[kTileRanks];
+    __shared__ int32_t s_lcp[kTileRanks];
+    ChunkSum total = chunk_empty();
+    const uint32_t tiles = (n + kTileRanks - 1) / kTileRanks;
+    const uint32_t t0 = blockIdx.x * kTilesPerGroup, t1 = min(tiles, t0 + kTilesPerGroup);
+    for (uint32_t t = t0; t < t1; ++t) {
+        const uint32_t base = t * kTileRanks;
+        const uint32_t cnt = min(kTileRanks, n - base);
+        int any = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < kChunk; ++i) {
+            const uint32_t j = i * kBlock + threadIdx.x;
+            if (j < cnt) {
+                const int32_t v = lcp[base + j];
+                s_lcp[j] = v;
+                uint32_t p;
+                any |= v > 0 && !run_start(base + j, v, start, P, lmax, &p);
+            }
+        }
+        any = __syncthreads_or(any);
+        if (!any) {
+            if (threadIdx.x == 0) {
+                const uint32_t r = base + cnt - 1;
+                const int32_t q = sa[r];
+                const uint32_t p = find_pair(start, P, r);
+                ChunkSum c = chunk_empty();
+                c.has_b = 1;
+                c.tail = RunSum{q, in_b(start, alen, p, (uint32_t)q) ? 1 : 0, INT_MAX, -1};
+                total = chunk_combine(total, c, start, P, best);
+            }
+            __syncthreads();
+            continue;
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < kChunk; ++i) {
+            const uint32_t j = i * kBlock + threadIdx.x;
+            if (j < cnt) s_sa[j] = sa[base + j];
+        }
+        __syncthreads();
+        ChunkSum c = chunk_empty();
+        const uint32_t j0 = threadIdx.x * kChunk;
+        for (uint32_t j = j0; j < min(cnt, j0 + kChunk); ++j) {
+            const int32_t q = s_sa[j];
+            uint32_t p;
+            const bool starts = run_start(base + j, s_lcp[j], start, P, lmax, &p);
+            const RunSum e{q, in_b(start, alen, p, (uint32_t)q) ? 1 : 0, INT_MAX, -1};
+            if (starts) {
+                if (c.has_b) finalize(c.tail, start, P, best);
+                c.has_b = 1;
+                c.tail = e;
+            } else if (c.has_b) {
+                c.tail = run_merge(c.tail, e);
+            } else {
+                c.head = run_merge(c.head, e);
+            }
+        }
+        reduce_chunks(s_sum, c, start, P, best);
+        if (threadIdx.x == 0) total = chunk_combine(total, s_sum[0], start, P, best);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_runs_final(const ChunkSum *__restrict__ in, uint32_t count,
+                                                           const int32_t *__restrict__ start, uint32_t P,
+                                                           unsigned long long *__restrict__ best) {
+    __shared__ ChunkSum s_sum[kBlock];
+    const uint32_t per = (count + kBlock - 1) / kBlock;
+    const uint32_t b = min(count, threadIdx.x * per), e = min(count, b + per);
+    ChunkSum c = chunk_empty();
+    for (uint32_t i = b; i < e; ++i) c = chunk_combine(c, in[i], start, P, best);
+    reduce_chunks(s_sum, c, start, P, best);
+    if (threadIdx.x == 0 && s_sum[0].has_b) finalize(s_sum[0].tail, start, P, best);
+}
+
+// One lor_overlap record per pair (offsets inside A_p / B_p).
+__global__ __launch_bounds__(kBlock) void k_pair_records(const int32_t *__restrict__ start,
+                                                         const int32_t *__restrict__ alen, uint32_t P,
+                                                         const uint32_t *__restrict__ lmax,
+                                                         const unsigned long long *__restrict__ best,
+                                                         lor_overlap *__restrict__ out) {
+    for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < P; p += gridDim.x * kBlock) {
+        lor_overlap o;
+        o.length = 0;
+        o.seq_p = o.seq_q = -1;
+        o.off_p = o.off_q = -1;
+        const unsigned long long bq = best[p];
+        if (lmax[p] > 0 && bq != ~0ull) {
+            const uint32_t x = (uint32_t)(bq >> 32), y = (uint32_t)bq;
+            const uint32_t s0 = (uint32_t)start[p], a = (uint32_t)alen[p];
+            o.length = lmax[p];
+            o.seq_p = x > s0 + a ? 1 : 0;
+            o.off_p = o.seq_p ? (int64_t)(x - s0 - a - 1) : (int64_t)(x - s0);
+            o.seq_q = y > s0 + a ? 1 : 0;
+            o.off_q = o.seq_q ? (int64_t)(y - s0 - a - 1) : (int64_t)(y - s0);
+        }
+        out[p] = o;
+    }
+}
+
+struct BatchPlan {
+    uint64_t N;
+    uint32_t P;
+};
+
+}  // namespace
+
+size_t batch_workspace(uint64_t total_bases, uint32_t P) {
+    const uint64_t N = total_bases + 2ull * P;
+    Arena ar;   // measuring
+    ar.top = kHeaderBytes;
+    ar.take<uint16_t>(N);                       // tagged text
+    ar.take<int32_t>(N);                        // SA
+    ar.take<int32_t>(N);                        // LCP
+    ar.take<int32_t>((size_t)P + 1);            // start
+    ar.take<int32_t>(P);                        // alen
+    ar.take<int64_t>(2ull * P);                 // src offsets
+    ar.take<uint32_t>(P);                       // lmax
+    ar.take<unsigned long long>(P);             // best
+    const size_t fixed = ar.top;
+    const size_t scan = (N + kGroupRanks - 1) / kGroupRanks * sizeof(ChunkSum) + 4096;
+    size_t phase = dc3_workspace_bound(N);
+    phase = std::max(phase, lcp_workspace(N) + 4096);
+    phase = std::max(phase, scan);
+    return fixed + phase + 4096;
+}
+
+lor_status batch_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t P, lor_overlap *out, void *ws,
+                         size_t ws_bytes, hipStream_t s) {
+    uint64_t N = 0;
+    std::vector<int32_t> h_start(P + 1), h_alen(P);
+    std::vector<int64_t> h_src(2 * (size_t)P);
+    for (uint32_t p = 0; p < P; ++p) {
+        const int64_t a = offsets[2 * p + 1] - offsets[2 * p], b = offsets[2 * p + 2] - offsets[2 * p + 1];
+        h_start[p] = (int32_t)N;
+        h_alen[p] = (int32_t)a;
+        h_src[2 * p] = offsets[2 * p];
+        h_src[2 * p + 1] = offsets[2 * p + 1];
+        N += (uint64_t)(a + b + 2);
+    }
+    h_start[P] = (int32_t)N;
+
+    Arena ar;
+    ar.base = static_cast<char *>(ws);
+    ar.cap = ws_bytes;
+    ar.top = kHeaderBytes;
+    uint32_t *hdr = static_cast<uint32_t *>(ws);
+    uint16_t *text;
+    int32_t *sa, *lcp, *start, *alen;
+    int64_t *src;
+    uint32_t *lmax;
+    unsigned long long *best;
+    LOR_TAKE(ar, uint16_t, N, text);
+    LOR_TAKE(ar, int32_t, N, sa);
+    LOR_TAKE(ar, int32_t, N, lcp);
+    LOR_TAKE(ar, int32_t, (size_t)P + 1, start);
+    LOR_TAKE(ar, int32_t, P, alen);
+    LOR_TAKE(ar, int64_t, 2ull * P, src);
+    LOR_TAKE(ar, uint32_t, P, lmax);
+    LOR_TAKE(ar, unsigned long long, P, best);
+    const size_t phase = ar.mark();
+
+    LOR_HIP(hipMemcpyAsync(start, h_start.data(), (P + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LOR_HIP(hipMemcpyAsync(alen, h_alen.data(), P * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LOR_HIP(hipMemcpyAsync(src, h_src.data(), 2ull * P * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    LOR_TRY(zero_words(hdr, 16, s));
+    LOR_LAUNCH("k_join_pairs", 3.0 * N, s,
+               hipLaunchKernelGGL(k_join_pairs, dim3(grid_for(N)), dim3(kBlock), 0, s, seqs, start, alen, src, P,
+                                  (uint32_t)N, text, hdr));
+    // DC3 reads back one word per level, which also orders the host copies above
+    LOR_TRY(dc3_u16(text, (uint32_t)N, 8u * (P - 1) + 6u, sa, ar, hdr, s));
+    ar.release(phase);
+    LOR_TRY(lcp_build_u16(text, (uint32_t)N, sa, lcp, nullptr, ar, s));
+    ar.release(phase);
+
+    const uint32_t groups = div_up(N, kGroupRanks);
+    ChunkSum *sums;
+    LOR_TAKE(ar, ChunkSum, (size_t)groups + 1, sums);
+    LOR_LAUNCH("k_pair_init", 8.0 * P, s,
+               hipLaunchKernelGGL(k_pair_init, dim3(grid_for(P)), dim3(kBlock), 0, s, P, lmax, best));
+    LOR_LAUNCH("k_seg_max", 8.0 * N, s,
+               hipLaunchKernelGGL(k_seg_max, dim3(grid_for(N)), dim3(kBlock), 0, s, sa, lcp, (uint32_t)N, start, alen,
+                                  P, lmax));
+    LOR_LAUNCH("k_seg_runs", 4.0 * N, s,
+               hipLaunchKernelGGL(k_seg_runs, dim3(groups), dim3(kBlock), 0, s, sa, lcp, (uint32_t)N, start, alen, P,
+                                  lmax, best, sums));
+    LOR_LAUNCH("k_seg_runs_final", (double)groups * sizeof(ChunkSum), s,
+               hipLaunchKernelGGL(k_seg_runs_final, dim3(1), dim3(kBlock), 0, s, sums, groups, start, P, best));
+    LOR_LAUNCH("k_pair_records", 32.0 * P, s,
+               hipLaunchKernelGGL(k_pair_records, dim3(grid_for(P)), dim3(kBlock), 0, s, start, alen, P, lmax, best,
+                                  out));
+    LOR_HIP(hipStreamSynchronize(s));   // host tables above must outlive their copies
+    return LOR_OK;
+}
+
+}  // namespace lor

@@ -64,6 +64,36 @@ template <> __device__ __forceinline__ uint32_t sym<uint8_t>(const uint8_t *t, u
 template <> __device__ __forceinline__ uint32_t sym<int32_t>(const int32_t *t, uint32_t n, uint32_t i) {
     return i < n ? (uint32_t)t[i] : 0u;
 }
+// Pair-tagged texts of the batched path: symbol = 8 * pair + code, code 1..6.
+template <> __device__ __forceinline__ uint32_t sym<uint16_t>(const uint16_t *t, uint32_t n, uint32_t i) {
+    return i < n ? (uint32_t)t[i] : 0u;
+}
+
+// Packed key of the triple at sample position p.
+// Byte and int32 texts: the three symbols, b bits each.
+// Pair-tagged texts: the pair tag, then the three codes (3 bits each), a code
+// of the next pair reading 0. Such a code only follows the pair's last or
+// second-to-last symbol, whose own prefix (ending in the pair's unique final
+// separator) already decides every comparison, so names keep the order and
+// equality of the full tagged triples while the key stays tag + 9 bits.
+template <typename CH> struct Triple {
+    static int key_bits(int b) { return 3 * b; }
+    template <typename K>
+    __device__ static K pack(const CH *t, const Dims &d, int b, uint32_t p) {
+        return ((K)sym(t, d.n, p) << (2 * b)) | ((K)sym(t, d.n, p + 1) << b) | (K)sym(t, d.n, p + 2);
+    }
+};
+template <> struct Triple<uint16_t> {
+    static int key_bits(int b) { return b + 6; }   // b = 3 + tag bits
+    template <typename K>
+    __device__ static K pack(const uint16_t *t, const Dims &d, int, uint32_t p) {
+        const uint32_t s0 = sym(t, d.n, p), s1 = sym(t, d.n, p + 1), s2 = sym(t, d.n, p + 2);
+        const uint32_t tag = s0 >> 3;
+        const uint32_t c1 = (s1 >> 3) == tag ? (s1 & 7u) : 0u;
+        const uint32_t c2 = (s2 >> 3) == tag && c1 ? (s2 & 7u) : 0u;
+        return (K)((tag << 9) | ((s0 & 7u) << 6) | (c1 << 3) | c2);
+    }
+};
 
 __device__ __forceinline__ void group_tiles(uint32_t items, uint32_t groups, uint32_t g, uint32_t *t0,
                                             uint32_t *t1) {
@@ -133,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_keys(const CH *__restrict__ t
         const uint32_t p = d.pos_of(idx);
         K key;
         if (mode == 0) {
-            key = ((K)sym(t, d.n, p) << (2 * b)) | ((K)sym(t, d.n, p + 1) << b) | (K)sym(t, d.n, p + 2);
+            key = Triple<CH>::template pack<K>(t, d, b, p);
         } else {
             key = (K)sym(t, d.n, p + (uint32_t)delta);
         }
@@ -236,8 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_name_write(const CH *__restrict__ t,
 // written in R-index order (streaming) instead of scattered from sorted order.
 template <typename CH>
 __device__ __forceinline__ uint32_t triple_key(const CH *t, const Dims &d, int b, uint32_t idx) {
-    const uint32_t p = d.pos_of(idx);
-    return (sym(t, d.n, p) << (2 * b)) | (sym(t, d.n, p + 1) << b) | sym(t, d.n, p + 2);
+    return Triple<CH>::template pack<uint32_t>(t, d, b, d.pos_of(idx));
 }
 
 template <typename CH>
@@ -307,6 +336,7 @@ __device__ __forceinline__ uint32_t rank_at(const int32_t *rank12, const Dims &d
 template <typename CH> struct Rec;
 template <> struct Rec<uint8_t> { uint4 a; };
 template <> struct Rec<int32_t> { uint4 a, b; };
+template <> struct Rec<uint16_t> { uint4 a, b; };
 
 template <typename CH>
 __global__ __launch_bounds__(kBlock) void k_records(const CH *__restrict__ t, Dims d,
@@ -356,6 +386,10 @@ template <> __device__ __forceinline__ Key4 key_of<uint8_t>(const Rec<uint8_t> *
 }
 template <> __device__ __forceinline__ Key4 key_of<int32_t>(const Rec<int32_t> *rec, uint32_t pos) {
     const Rec<int32_t> x = rec[pos / 3u];
+    return make_key(pos % 3u, x.a.x, x.a.y, x.a.z, x.a.w, x.b.x, x.b.y, x.b.z);
+}
+template <> __device__ __forceinline__ Key4 key_of<uint16_t>(const Rec<uint16_t> *rec, uint32_t pos) {
+    const Rec<uint16_t> x = rec[pos / 3u];
     return make_key(pos % 3u, x.a.x, x.a.y, x.a.z, x.a.w, x.b.x, x.b.y, x.b.z);
 }
 
@@ -531,7 +565,8 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     const size_t mark_tmp = ar.mark();
 
     // ---- Step 1: sort the sample triples
-    KeyMode km = (3 * b <= 32) ? KM_U32 : (3 * b <= 64 ? KM_U64 : KM_STAGED);
+    const int kb = Triple<CH>::key_bits(b);
+    KeyMode km = (kb <= 32) ? KM_U32 : (kb <= 64 ? KM_U64 : KM_STAGED);
     if (!run) km = KM_U64;   // measuring: the largest footprint
     uint32_t *counts;
     LOR_TAKE(ar, uint32_t, radix_counts_words(d.m) + kMaxScanGroups + 64, counts);
@@ -539,13 +574,12 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     uint32_t *tmpv;
     LOR_TAKE(ar, uint32_t, d.m, tmpv);
     const int per_sym = radix_passes(0, b);
-    const int passes = d.m <= 1 ? 0 : (km == KM_STAGED ? 3 * per_sym : radix_passes(0, 3 * b));
+    const int passes = d.m <= 1 ? 0 : (km == KM_STAGED ? 3 * per_sym : radix_passes(0, kb));
     uint32_t *v0 = (passes % 2 == 0) ? (uint32_t *)sa12 : tmpv;
     uint32_t *v1 = (passes % 2 == 0) ? tmpv : (uint32_t *)sa12;
     const uint32_t g_el = grid_for(d.m);
     uint32_t hmax = 0;
 
-    const int kb = 3 * b;
     const bool use_table = run && kb <= 24 && ((uint64_t)1 << kb) <= 2ull * d.m + 65536ull;
     if (use_table) {
         const uint32_t words = max(1u, (uint32_t)(((uint64_t)1 << kb) / 32));
@@ -578,7 +612,7 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
                        hipLaunchKernelGGL((k_sample_keys<CH, uint64_t>), dim3(g_el), dim3(kBlock), 0, s, t, d, b,
                                           0, 0, k0, v0));
             bool alt;
-            LOR_TRY(radix_sort<uint64_t>(k0, v0, k1, v1, d.m, 0, 3 * b, counts, s, &alt));
+            LOR_TRY(radix_sort<uint64_t>(k0, v0, k1, v1, d.m, 0, kb, counts, s, &alt));
             uint64_t *ks = alt ? k1 : k0;
             if ((alt ? v1 : v0) != (uint32_t *)sa12) {
                 set_error("internal: sorted sample order not in its buffer");
@@ -613,7 +647,7 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
                 LOR_LAUNCH("k_sample_keys", (double)d.m * 8 + (double)n * sizeof(CH), s,
                            hipLaunchKernelGGL((k_sample_keys<CH, uint32_t>), dim3(g_el), dim3(kBlock), 0, s, t, d,
                                               b, 0, 0, kc, vc));
-                LOR_TRY(radix_sort<uint32_t>(kc, vc, ka, va, d.m, 0, 3 * b, counts, s, &alt));
+                LOR_TRY(radix_sort<uint32_t>(kc, vc, ka, va, d.m, 0, kb, counts, s, &alt));
                 swap_if(alt);
             } else {
                 // LSD over whole symbols: t_{i+2}, then t_{i+1}, then t_i.
@@ -750,6 +784,11 @@ lor_status dc3_u8(const uint8_t *text, uint32_t n, uint32_t alphabet, int32_t *s
 lor_status dc3_i32(const int32_t *text, uint32_t n, uint32_t alphabet, int32_t *sa, Arena &ar, uint32_t *hdr,
                    hipStream_t s) {
     return dc3_level<int32_t>(text, n, alphabet, sa, ar, hdr, s, 0);
+}
+
+lor_status dc3_u16(const uint16_t *text, uint32_t n, uint32_t alphabet, int32_t *sa, Arena &ar, uint32_t *hdr,
+                   hipStream_t s) {
+    return dc3_level<uint16_t>(text, n, alphabet, sa, ar, hdr, s, 0);
 }
 
 size_t dc3_workspace_bound(uint64_t n) {

@@ -45,8 +45,8 @@ __global__ __launch_bounds__(kBlock) void k_phi_place(const uint64_t *__restrict
     if (p < n) isa_phi[p] = make_int2((int32_t)ranks[i], (int32_t)(uint32_t)k);
 }
 
-// 8 text bytes starting at byte offset a; requires a + 16 <= n and an
-// 8-byte aligned text (two aligned loads, then a funnel shift).
+// 8 text bytes starting at byte offset a; requires a + 16 <= text bytes and
+// an 8-byte aligned text (two aligned loads, then a funnel shift).
 __device__ __forceinline__ uint64_t load8(const uint8_t *__restrict__ t, uint32_t a) {
     const uint64_t *w = reinterpret_cast<const uint64_t *>(t + (a & ~7u));
     const uint32_t sh = (a & 7u) * 8u;
@@ -54,22 +54,27 @@ __device__ __forceinline__ uint64_t load8(const uint8_t *__restrict__ t, uint32_
     return sh ? (lo >> sh) | (hi << (64u - sh)) : lo;
 }
 
-// Common-prefix length of suffixes i and j, knowing the first h symbols agree.
-__device__ __forceinline__ uint32_t extend(const uint8_t *__restrict__ t, uint32_t n, uint32_t i, uint32_t j,
-                                           uint32_t h, bool wide) {
+// Common-prefix length of suffixes i and j (in symbols), knowing the first h
+// symbols agree. Wide mode compares 8 bytes (8 / sizeof(CH) symbols) a step.
+template <typename CH>
+__device__ __forceinline__ uint32_t extend(const CH *__restrict__ t, uint32_t n, uint32_t i, uint32_t j, uint32_t h,
+                                           bool wide) {
+    constexpr uint32_t per = 8 / sizeof(CH);
     const uint32_t lim = n - max(i, j);   // symbols available in both
     if (wide) {
-        while (h + 16 <= lim) {
-            const uint64_t x = load8(t, i + h) ^ load8(t, j + h);
-            if (x) return h + (uint32_t)(__builtin_ctzll(x) >> 3);
-            h += 8;
+        const uint8_t *tb = reinterpret_cast<const uint8_t *>(t);
+        while (h + 2 * per <= lim) {
+            const uint64_t x = load8(tb, (i + h) * (uint32_t)sizeof(CH)) ^ load8(tb, (j + h) * (uint32_t)sizeof(CH));
+            if (x) return h + (uint32_t)(__builtin_ctzll(x) / (8 * sizeof(CH)));
+            h += per;
         }
     }
     while (h < lim && t[i + h] == t[j + h]) ++h;
     return h;
 }
 
-__global__ __launch_bounds__(kBlock) void k_plcp(const uint8_t *__restrict__ t, uint32_t n,
+template <typename CH>
+__global__ __launch_bounds__(kBlock) void k_plcp(const CH *__restrict__ t, uint32_t n,
                                                  const int2 *__restrict__ isa_phi, int32_t *__restrict__ plcp,
                                                  int32_t *__restrict__ isa_out, int wide) {
     constexpr uint32_t span = kWave * kPlcpSteps;
@@ -97,8 +102,9 @@ __global__ __launch_bounds__(kBlock) void k_plcp(const uint8_t *__restrict__ t, 
 
 size_t lcp_workspace(uint64_t n) { return (size_t)n * 28 + radix_counts_words(n) * 4 + 4096; }
 
-lor_status lcp_build(const uint8_t *text, uint32_t n, const int32_t *sa, int32_t *lcp, int32_t *isa, Arena &ar,
-                     hipStream_t s) {
+template <typename CH>
+lor_status lcp_build_t(const CH *text, uint32_t n, const int32_t *sa, int32_t *lcp, int32_t *isa, Arena &ar,
+                       hipStream_t s) {
     uint64_t *keys, *keys2;       // keys later holds the (ISA, Phi) pairs
     uint32_t *vals2, *plcp, *isa_tmp, *counts;
     LOR_TAKE(ar, uint64_t, n, keys);
@@ -119,12 +125,22 @@ lor_status lcp_build(const uint8_t *text, uint32_t n, const int32_t *sa, int32_t
     LOR_LAUNCH("k_phi_place", (double)n * 20, s,
                hipLaunchKernelGGL(k_phi_place, dim3(xcd_grid(n)), dim3(kBlock), 0, s, keys2, vals2, n, isa_phi));
     const uint32_t waves = div_up(n, kWave * kPlcpSteps);
-    LOR_LAUNCH("k_plcp", (double)n * 17, s,
-               hipLaunchKernelGGL(k_plcp, dim3(grid_for((uint64_t)waves * kWave)), dim3(kBlock), 0, s, text, n, isa_phi,
-                                  reinterpret_cast<int32_t *>(plcp), isa_w, wide));
+    LOR_LAUNCH("k_plcp", (double)n * (16 + sizeof(CH)), s,
+               hipLaunchKernelGGL(k_plcp<CH>, dim3(grid_for((uint64_t)waves * kWave)), dim3(kBlock), 0, s, text, n,
+                                  isa_phi, reinterpret_cast<int32_t *>(plcp), isa_w, wide));
     uint32_t *tmp_idx = reinterpret_cast<uint32_t *>(keys2);
     return bucketed_scatter(lcp, n, reinterpret_cast<const uint32_t *>(isa_w), plcp, 0, n, tmp_idx, tmp_idx + n,
                             counts, s);
+}
+
+lor_status lcp_build(const uint8_t *text, uint32_t n, const int32_t *sa, int32_t *lcp, int32_t *isa, Arena &ar,
+                     hipStream_t s) {
+    return lcp_build_t<uint8_t>(text, n, sa, lcp, isa, ar, s);
+}
+
+lor_status lcp_build_u16(const uint16_t *text, uint32_t n, const int32_t *sa, int32_t *lcp, int32_t *isa, Arena &ar,
+                         hipStream_t s) {
+    return lcp_build_t<uint16_t>(text, n, sa, lcp, isa, ar, s);
 }
 
 }  // namespace lor

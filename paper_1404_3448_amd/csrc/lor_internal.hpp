@@ -172,6 +172,9 @@ lor_status dc3_u8(const uint8_t *text, uint32_t n, uint32_t alphabet, int32_t *s
                   uint32_t *hdr_dev, hipStream_t s);
 lor_status dc3_i32(const int32_t *text, uint32_t n, uint32_t alphabet, int32_t *sa, Arena &ar,
                    uint32_t *hdr_dev, hipStream_t s);
+// Pair-tagged 16-bit text of the batched path (symbol = 8 * pair + code).
+lor_status dc3_u16(const uint16_t *text, uint32_t n, uint32_t alphabet, int32_t *sa, Arena &ar,
+                   uint32_t *hdr_dev, hipStream_t s);
 size_t dc3_workspace_bound(uint64_t n);
 
 // Zero `count` words on the stream with a kernel (no memset nodes).
@@ -186,6 +189,8 @@ lor_status join_text(const uint8_t *seqs, const int64_t *offsets, int32_t k, uin
 size_t lcp_workspace(uint64_t n);
 lor_status lcp_build(const uint8_t *text, uint32_t n, const int32_t *sa, int32_t *lcp, int32_t *isa,
                      Arena &ar, hipStream_t s);
+lor_status lcp_build_u16(const uint16_t *text, uint32_t n, const int32_t *sa, int32_t *lcp, int32_t *isa,
+                         Arena &ar, hipStream_t s);
 
 // ------------------------------------------------------------------ RMQ
 uint64_t rmq_level_offset(uint64_t n, int level);   // entries before `level` (levels from 1)
@@ -201,6 +206,12 @@ struct SeqStarts {           // joined start of every sequence, plus N
     int32_t k;
 };
 size_t overlap_workspace(uint64_t n);
+
+// ------------------------------------------------------------ batched
+constexpr uint32_t kMaxPairs = 8191;   // tags 0..8190: 8 * tag + 6 fits 16 bits
+size_t batch_workspace(uint64_t total_bases, uint32_t num_pairs);
+lor_status batch_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t num_pairs, lor_overlap *out,
+                         void *ws, size_t ws_bytes, hipStream_t s);
 lor_status overlap_scan(const int32_t *sa, const int32_t *lcp, uint32_t n, const SeqStarts &st,
                         Arena &ar, hipStream_t s, int64_t result[5]);
 

@@ -83,6 +83,8 @@ def lib():
         "lor_rmq_query": ([ctypes.POINTER(lor_rmq), P, P, I32, P, P, I64, P, P, P], I32),
         "lor_longest_overlap_workspace": ([I64, I32], SZ),
         "lor_longest_overlap": ([P, P, I64, P, I32, ctypes.POINTER(lor_overlap), P, SZ, P], I32),
+        "lor_longest_overlap_batched_workspace": ([I64, I32], SZ),
+        "lor_longest_overlap_batched": ([P, P, I32, P, P, P, SZ, P], I32),
         "lor_sort_pairs_workspace": ([I64, I32], SZ),
         "lor_sort_pairs_u32": ([P, P, I64, I32, I32, P, SZ, P], I32),
         "lor_sort_pairs_u64": ([P, P, I64, I32, I32, P, SZ, P], I32),
@@ -288,6 +290,40 @@ def lor_longest_overlap(sa, lcp, offsets, ws=None, stream=None) -> tuple:
                                    _ptr(ws), ws.numel() * ws.element_size(), _stream(stream))
     _check("lor_longest_overlap", st)
     return (int(out.length), int(out.seq_p), int(out.off_p), int(out.seq_q), int(out.off_q))
+
+
+# ------------------------------------------------ batched longest overlap
+
+def lor_longest_overlap_batched_workspace(total_bases: int, num_pairs: int) -> int:
+    return int(lib().lor_longest_overlap_batched_workspace(total_bases, num_pairs))
+
+
+def lor_longest_overlap_batched(seqs, offsets, out=None, ws=None, stream=None):
+    """Longest overlap of every pair (sequences 2p, 2p+1). Returns an int64
+    device tensor [num_pairs, 4] of (length, off_p, off_q, seq_p | seq_q << 8)
+    views of the lor_overlap records (see records_to_tuples)."""
+    import torch
+    o = _offsets(offsets)
+    if (o.size - 1) % 2:
+        raise ValueError("offsets: need int64[2 * num_pairs + 1]")
+    P = (o.size - 1) // 2
+    _need(seqs, torch.uint8, int(o[-1]), "seqs")
+    if out is None:
+        out = torch.empty(P * ctypes.sizeof(lor_overlap), dtype=torch.uint8, device=seqs.device)
+    nbytes = lor_longest_overlap_batched_workspace(int(o[-1]), P)
+    ws = _workspace(nbytes, seqs.device, ws)
+    st = lib().lor_longest_overlap_batched(_ptr(seqs), o.ctypes.data_as(ctypes.c_void_p), P, None, _ptr(out),
+                                           _ptr(ws), ws.numel() * ws.element_size(), _stream(stream))
+    _check("lor_longest_overlap_batched", st)
+    return out
+
+
+def records_to_tuples(out) -> list:
+    """Device lor_overlap records -> [(length, seq_p, off_p, seq_q, off_q), ...]."""
+    raw = out.cpu().numpy().tobytes()
+    n = len(raw) // ctypes.sizeof(lor_overlap)
+    arr = (lor_overlap * n).from_buffer_copy(raw)
+    return [(int(r.length), int(r.seq_p), int(r.off_p), int(r.seq_q), int(r.off_q)) for r in arr]
 
 
 # ------------------------------------------------------------- radix sort
