@@ -9,6 +9,10 @@ tandem repeats over ~10% of each), joined length N = 1,073,741,840, with
 10,000,000 uniform (i, j) queries (seed 3). `value` is N / step time in
 Msuffixes/s for the whole step; the SA+LCP-only rate is reported beside it.
 
+After the timed steps, `batched` reports 4096 independent pairs (seed 4)
+through one batched call against a loop of the plain per-pair path, and
+`cpu_baseline` times the CPU oracle on a bounded sample of the same text.
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -59,6 +63,59 @@ def cpu_baseline(seqs, seq_cut: int, nseq: int, threads: int) -> dict:
             "seconds": round(dt, 3)}
 
 
+def bench_batched(lor, synth, torch, reps: int = 3) -> dict:
+    """4096 pairs (totals log-uniform in [1e3, 1e6], seed 4): one batched call
+    versus a loop of the plain per-pair path, resident inputs, same results."""
+    import ctypes
+
+    t0 = time.perf_counter()
+    ws_pairs = synth.batched_pairs()
+    seqs = [s for w in ws_pairs for s in w.seqs]
+    offs = np.concatenate([[0], np.cumsum([s.size for s in seqs])]).astype(np.int64)
+    P = len(ws_pairs)
+    total = int(offs[-1])
+    log(f"batched workload: {P} pairs, {total} bases, generated in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    d = torch.from_numpy(np.concatenate(seqs)).to(dev)
+    out = torch.empty(P * ctypes.sizeof(lor.lor_overlap), dtype=torch.uint8, device=dev)
+    ws = torch.empty(lor.lor_longest_overlap_batched_workspace(total, P), dtype=torch.uint8, device=dev)
+    lor.lor_longest_overlap_batched(d, offs, out=out, ws=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        lor.lor_longest_overlap_batched(d, offs, out=out, ws=ws)
+    torch.cuda.synchronize()
+    batched_s = (time.perf_counter() - t) / reps
+    batched = lor.records_to_tuples(out)
+    del ws
+
+    nmax = max(w.joined_length for w in ws_pairs)
+    bmax = max(int(w.offsets[-1]) for w in ws_pairs)
+    joined = torch.empty(nmax, dtype=torch.uint8, device=dev)
+    sa = torch.empty(nmax, dtype=torch.int32, device=dev)
+    lcp = torch.empty(nmax, dtype=torch.int32, device=dev)
+    ws_sa = torch.empty(lor.lor_build_sa_workspace(bmax, 2), dtype=torch.uint8, device=dev)
+    ws_lcp = torch.empty(lor.lor_build_lcp_workspace(nmax), dtype=torch.uint8, device=dev)
+    ws_ov = torch.empty(lor.lor_longest_overlap_workspace(nmax, 2), dtype=torch.uint8, device=dev)
+    plain = []
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for p, w in enumerate(ws_pairs):
+        lo, hi = int(offs[2 * p]), int(offs[2 * p + 2])
+        sub = w.offsets
+        n = w.joined_length
+        s_, j_ = lor.lor_build_sa(d[lo:hi], sub, joined_out=joined, sa_out=sa, ws=ws_sa)
+        l_, _ = lor.lor_build_lcp(j_, s_, lcp_out=lcp, ws=ws_lcp)
+        plain.append(lor.lor_longest_overlap(s_, l_, sub, ws=ws_ov))
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t
+    return {"workload": f"{P} pairs, pair totals log-uniform in [1e3, 1e6], {total} bases (seed 4)",
+            "pairs": P, "bases": total,
+            "batched_ms": round(1e3 * batched_s, 3), "batched_pairs_per_s": round(P / batched_s, 1),
+            "plain_loop_ms": round(1e3 * plain_s, 3), "plain_loop_pairs_per_s": round(P / plain_s, 1),
+            "speedup": round(plain_s / batched_s, 2), "identical_to_plain": batched == plain}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +124,7 @@ def main():
     ap.add_argument("--workload", default="1g", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -167,12 +225,20 @@ def main():
                     "launch_ms_avg": round(dom["ms"] / dom["launches"], 4),
                     "alg_bytes_per_launch_avg": round(dom["bytes"] / dom["launches"])}
 
+    del table, ws_sa, ws_lcp, ws_ov, joined, sa, lcp, isa, qout, seqs, qi, qj
+    torch.cuda.empty_cache()
+    batched = None
+    if not args.no_batched:
+        log("batched vs plain loop ...")
+        batched = bench_batched(lor, synth, torch)
+        log(f"batched: {batched}")
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
-        cut = min(seq_len, 1 << 24)
+        cut = min(seq_len, 1 << 25)
         log("timing the CPU oracle sample ...")
-        cpu = cpu_baseline(w.seqs, cut, min(4, num_seqs), threads)
+        cpu = cpu_baseline(w.seqs, cut, min(8, num_seqs), threads)
 
     out = {
         "metric": METRIC,
@@ -197,6 +263,7 @@ def main():
         "overlap": list(ov),
         "roofline": roofline,
         "kernels": kern_out,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
