@@ -10,7 +10,8 @@ tandem repeats over ~10% of each), joined length N = 1,073,741,840, with
 Msuffixes/s for the whole step; the SA+LCP-only rate is reported beside it.
 
 After the timed steps, `batched` reports 4096 independent pairs (seed 4)
-through one batched call against a loop of the plain per-pair path, and
+through one batched call against a loop of the plain per-pair path,
+`serving` the continuous-batching loop under Poisson load (p50/p99), and
 `cpu_baseline` times the CPU oracle on a bounded sample of the same text.
 
 Prints one JSON line on stdout; progress goes to stderr.
@@ -116,6 +117,27 @@ def bench_batched(lor, synth, torch, reps: int = 3) -> dict:
             "speedup": round(plain_s / batched_s, 2), "identical_to_plain": batched == plain}
 
 
+def bench_serving(seed: int = 5) -> dict:
+    """Poisson requests (each sequence 1e4..4e6 bases, log-uniform; 30% keep
+    state and send 10^4 follow-up queries after an exponential delay of mean
+    50 ms) at 0.7x the closed-loop capacity, 200 GB HBM budget."""
+    from paper_1404_3448_amd import serve
+
+    backlog = serve.make_requests(seed=seed + 100, count=64, qps=1e9)
+    for r in backlog:
+        r.arrival = 0.0
+    srv = serve.Server(slots=4)
+    cap = srv.run(backlog)
+    capacity = cap["pairs_per_s"]
+    qps = 0.7 * capacity
+    reqs = serve.make_requests(seed=seed, count=400, qps=qps)
+    stats = serve.Server(slots=4).run(reqs)
+    stats.update({"capacity_pairs_per_s": capacity, "offered_qps": round(qps, 1),
+                  "workload": "Poisson arrivals at 0.7x capacity; sequences log-uniform in [1e4, 4e6] bases; "
+                              "30% keep state, 10^4 follow-up queries each (seed 5)"})
+    return stats
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +147,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -233,6 +256,12 @@ def main():
         batched = bench_batched(lor, synth, torch)
         log(f"batched: {batched}")
 
+    serving = None
+    if not args.no_serving:
+        log("serving ...")
+        serving = bench_serving()
+        log(f"serving: {serving}")
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
@@ -264,6 +293,7 @@ def main():
         "roofline": roofline,
         "kernels": kern_out,
         "batched": batched,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -1,0 +1,42 @@
+"""Serving on the GPU: every result (and follow-up answer) is the same served
+alone and in a concurrent mix, and equals the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1404_3448_amd import lor, serve
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def alone(req):
+    d = torch.from_numpy(np.concatenate([req.a, req.b])).cuda()
+    r = lor.longest_overlap_region(d, req.offsets, want_isa=True)
+    fol = None
+    if req.keep:
+        rmq = lor.lor_rmq_build(r["lcp"])
+        got, _ = lor.lor_rmq_query(rmq, r["lcp"], r["isa"], 1, torch.from_numpy(req.followup[0]).cuda(),
+                                   torch.from_numpy(req.followup[1]).cuda())
+        fol = got.cpu().numpy()
+    return r["overlap"], fol
+
+
+def test_alone_equals_mix():
+    reqs = serve.make_requests(seed=5, count=80, qps=400.0, lo=1e3, hi=3e5, queries=2000, followup_mean=0.01)
+    srv = serve.Server(slots=4, small_bases=100_000, batch_max=16)
+    stats = srv.run(reqs)
+    assert stats["rejected"] == 0
+    assert stats["batched_requests"] > 0 and stats["followups"] > 0
+    for r in reqs:
+        ov, fol = alone(r)
+        assert r.result == ov, r.rid
+        if r.keep:
+            assert np.array_equal(r.followup_result, fol), r.rid
+    for r in reqs[:6]:
+        joined = oracle.join(np.concatenate([r.a, r.b]), r.offsets)
+        sa = oracle.suffix_array(joined)
+        assert r.result == oracle.overlap(sa, oracle.lcp(joined, sa), r.offsets)
+        if r.keep:
+            assert np.array_equal(r.followup_result, oracle.pair_queries(joined, *r.followup))
