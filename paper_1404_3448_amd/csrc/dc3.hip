@@ -154,62 +154,50 @@ __global__ __launch_bounds__(kBlock) void k_join(const uint8_t *__restrict__ seq
 
 // ------------------------------------------------------- Step 1: keys
 
-// mode 0: packed triple key; mode 1: the single symbol at p + delta.
+// mode 0: packed triple key (t_i, t_{i+1}, t_{i+2});
+// mode 1: packed pair (t_{i+1}, t_{i+2}) of b-bit symbols, the first stage of
+// wide triples.
 template <typename CH, typename K>
 __global__ __launch_bounds__(kBlock) void k_sample_keys(const CH *__restrict__ t, Dims d, int b, int mode,
-                                                        int delta, K *__restrict__ keys,
-                                                        uint32_t *__restrict__ vals) {
+                                                        K *__restrict__ keys, uint32_t *__restrict__ vals) {
     for (uint32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < d.m; idx += gridDim.x * kBlock) {
         const uint32_t p = d.pos_of(idx);
         K key;
         if (mode == 0) {
             key = Triple<CH>::template pack<K>(t, d, b, p);
         } else {
-            key = (K)sym(t, d.n, p + (uint32_t)delta);
+            key = ((K)sym(t, d.n, p + 1) << b) | (K)sym(t, d.n, p + 2);
         }
         keys[idx] = key;
         vals[idx] = idx;
     }
 }
 
-// keys[r] = symbol at pos(vals[r]) + delta (re-keying between LSD stages).
+// Second stage of wide triples: keys[r] = (t_i << 32) | rank of the pair
+// (t_{i+1}, t_{i+2}) of sorted entry r.
 template <typename CH>
-__global__ __launch_bounds__(kBlock) void k_rekey(const CH *__restrict__ t, Dims d, int delta,
-                                                  const uint32_t *__restrict__ vals,
-                                                  uint32_t *__restrict__ keys) {
+__global__ __launch_bounds__(kBlock) void k_pair_rekey(const CH *__restrict__ t, Dims d,
+                                                       const uint32_t *__restrict__ vals,
+                                                       const uint32_t *__restrict__ pair_rank,
+                                                       uint64_t *__restrict__ keys) {
     for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < d.m; r += gridDim.x * kBlock)
-        keys[r] = sym(t, d.n, d.pos_of(vals[r]) + (uint32_t)delta);
+        keys[r] = ((uint64_t)sym(t, d.n, d.pos_of(vals[r])) << 32) | pair_rank[r];
 }
 
 // ------------------------------------------------------ Step 1: naming
 
-// A sorted entry starts a new name when its triple differs from the
-// previous entry's. GATHER: compare triples read from the text (keys hold
-// only part of the triple).
-template <typename CH, typename K, bool GATHER>
-__device__ __forceinline__ bool starts_name(const CH *t, const Dims &d, const K *keys,
-                                            const uint32_t *vals, uint32_t r, K cur, K prev) {
-    if (r == 0) return true;
-    if (!GATHER) return cur != prev;
-    const uint32_t p = d.pos_of(vals[r]), q = d.pos_of(vals[r - 1]);
-    return sym(t, d.n, p) != sym(t, d.n, q) || sym(t, d.n, p + 1) != sym(t, d.n, q + 1) ||
-           sym(t, d.n, p + 2) != sym(t, d.n, q + 2);
-}
-
-template <typename CH, typename K, bool GATHER>
-__global__ __launch_bounds__(kBlock) void k_name_count(const CH *__restrict__ t, Dims d,
-                                                       const K *__restrict__ keys,
-                                                       const uint32_t *__restrict__ vals,
-                                                       uint32_t groups, uint32_t *__restrict__ counts) {
+// A sorted entry starts a new name when its key differs from its
+// predecessor's (the keys hold whole triples, or a triple's first symbol and
+// the rank of its last two).
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_name_count(const K *__restrict__ keys, uint32_t m, uint32_t groups,
+                                                       uint32_t *__restrict__ counts) {
     __shared__ uint32_t s_tmp[kBlock / kWave];
     uint32_t t0, t1;
-    group_tiles(d.m, groups, blockIdx.x, &t0, &t1);
+    group_tiles(m, groups, blockIdx.x, &t0, &t1);
     uint32_t c = 0;
-    for (uint32_t r = t0 * kScanTile + threadIdx.x; r < min(d.m, t1 * kScanTile); r += kBlock) {
-        const K cur = keys[r];
-        const K prev = r ? keys[r - 1] : cur;
-        c += starts_name<CH, K, GATHER>(t, d, keys, vals, r, cur, prev);
-    }
+    for (uint32_t r = t0 * kScanTile + threadIdx.x; r < min(m, t1 * kScanTile); r += kBlock)
+        c += (r == 0) || keys[r] != keys[r - 1];
     uint32_t tot;
     dev::block_exclusive_sum(c, s_tmp, &tot);
     if (threadIdx.x == 0) counts[blockIdx.x] = tot;
@@ -217,28 +205,26 @@ __global__ __launch_bounds__(kBlock) void k_name_count(const CH *__restrict__ t,
 
 // names[r] = 1-based name of sorted entry r (written in sorted order; a
 // bucketed scatter then moves each name to its R-index).
-template <typename CH, typename K, bool GATHER>
-__global__ __launch_bounds__(kBlock) void k_name_write(const CH *__restrict__ t, Dims d,
-                                                       const K *__restrict__ keys,
-                                                       const uint32_t *__restrict__ vals,
-                                                       uint32_t groups, const uint32_t *__restrict__ counts,
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_name_write(const K *__restrict__ keys, uint32_t m, uint32_t groups,
+                                                       const uint32_t *__restrict__ counts,
                                                        uint32_t *__restrict__ names) {
     __shared__ uint32_t s_tmp[kBlock / kWave];
     uint32_t t0, t1;
-    group_tiles(d.m, groups, blockIdx.x, &t0, &t1);
+    group_tiles(m, groups, blockIdx.x, &t0, &t1);
     uint32_t base = counts[blockIdx.x];
     for (uint32_t tile = t0; tile < t1; ++tile) {
         const uint32_t r0 = tile * kScanTile + threadIdx.x * kScanItems;
         bool f[kScanItems];
         uint32_t c = 0;
-        K prev = (r0 > 0 && r0 < d.m) ? keys[r0 - 1] : K(0);
+        K prev = (r0 > 0 && r0 < m) ? keys[r0 - 1] : K(0);
 #pragma unroll
         for (int i = 0; i < kScanItems; ++i) {
             const uint32_t r = r0 + i;
             f[i] = false;
-            if (r < d.m) {
+            if (r < m) {
                 const K cur = keys[r];
-                f[i] = starts_name<CH, K, GATHER>(t, d, keys, vals, r, cur, prev);
+                f[i] = (r == 0) || cur != prev;
                 prev = cur;
             }
             c += f[i];
@@ -248,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_name_write(const CH *__restrict__ t,
 #pragma unroll
         for (int i = 0; i < kScanItems; ++i) {
             const uint32_t r = r0 + i;
-            if (r < d.m) {
+            if (r < m) {
                 name += f[i];
                 names[r] = name;
             }
@@ -573,8 +559,8 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     uint32_t *gcount = counts + radix_counts_words(d.m);
     uint32_t *tmpv;
     LOR_TAKE(ar, uint32_t, d.m, tmpv);
-    const int per_sym = radix_passes(0, b);
-    const int passes = d.m <= 1 ? 0 : (km == KM_STAGED ? 3 * per_sym : radix_passes(0, kb));
+    const int passes = d.m <= 1 ? 0
+                       : (km == KM_STAGED ? radix_passes(0, 2 * b) + radix_passes(32, 32 + b) : radix_passes(0, kb));
     uint32_t *v0 = (passes % 2 == 0) ? (uint32_t *)sa12 : tmpv;
     uint32_t *v1 = (passes % 2 == 0) ? tmpv : (uint32_t *)sa12;
     const uint32_t g_el = grid_for(d.m);
@@ -598,38 +584,69 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
         LOR_LAUNCH("k_name_table", (double)n * sizeof(CH) + 4.0 * d.m, s,
                    hipLaunchKernelGGL(k_name_table<CH>, dim3(g_el), dim3(kBlock), 0, s, t, d, b, bitmap, below, words,
                                       R));
-    } else if (km == KM_U64) {
+    } else if (km != KM_U32) {
+        // 64-bit keys: whole triples, or (for wide symbols) two stages.
         uint64_t *k0, *k1;
+        uint32_t *aux;
         LOR_TAKE(ar, uint64_t, d.m, k0);
         LOR_TAKE(ar, uint64_t, d.m, k1);
+        LOR_TAKE(ar, uint32_t, d.m, aux);
         if (!run) {
             // the bitmap path may take up to 2 x (2m + 65536) / 32 words plus scan space
             uint8_t *extra;
             LOR_TAKE(ar, uint8_t, (size_t)d.m / 2 + 16384 + kScanTmpWords * 4 + 1024, extra);
         }
         if (run) {
-            LOR_LAUNCH("k_sample_keys", (double)d.m * 12 + (double)n * sizeof(CH), s,
-                       hipLaunchKernelGGL((k_sample_keys<CH, uint64_t>), dim3(g_el), dim3(kBlock), 0, s, t, d, b,
-                                          0, 0, k0, v0));
-            bool alt;
-            LOR_TRY(radix_sort<uint64_t>(k0, v0, k1, v1, d.m, 0, kb, counts, s, &alt));
-            uint64_t *ks = alt ? k1 : k0;
-            if ((alt ? v1 : v0) != (uint32_t *)sa12) {
+            uint64_t *kc = k0, *ka = k1;
+            uint32_t *vc = v0, *va = v1;
+            bool alt = false;
+            auto swap_if = [&](bool x) {
+                if (x) {
+                    uint64_t *y = kc; kc = ka; ka = y;
+                    uint32_t *z = vc; vc = va; va = z;
+                }
+            };
+            const uint32_t G = scan_groups(d.m);
+            if (km == KM_U64) {
+                LOR_LAUNCH("k_sample_keys", (double)d.m * 12 + (double)n * sizeof(CH), s,
+                           hipLaunchKernelGGL((k_sample_keys<CH, uint64_t>), dim3(g_el), dim3(kBlock), 0, s, t, d, b,
+                                              0, kc, vc));
+                LOR_TRY(radix_sort<uint64_t>(kc, vc, ka, va, d.m, 0, kb, counts, s, &alt));
+                swap_if(alt);
+            } else {
+                // stage A: sort the pairs (t_{i+1}, t_{i+2}) and rank them
+                LOR_LAUNCH("k_sample_keys", (double)d.m * 12 + (double)n * sizeof(CH), s,
+                           hipLaunchKernelGGL((k_sample_keys<CH, uint64_t>), dim3(g_el), dim3(kBlock), 0, s, t, d, b,
+                                              1, kc, vc));
+                LOR_TRY(radix_sort<uint64_t>(kc, vc, ka, va, d.m, 0, 2 * b, counts, s, &alt));
+                swap_if(alt);
+                LOR_LAUNCH("k_name_count", (double)d.m * 8, s,
+                           hipLaunchKernelGGL(k_name_count<uint64_t>, dim3(G), dim3(kBlock), 0, s, kc, d.m, G,
+                                              gcount));
+                LOR_TRY(scan_block_totals(gcount, G, nullptr, s));
+                LOR_LAUNCH("k_name_write", (double)d.m * 12, s,
+                           hipLaunchKernelGGL(k_name_write<uint64_t>, dim3(G), dim3(kBlock), 0, s, kc, d.m, G, gcount,
+                                              aux));
+                // stage B: (t_i, pair rank), sorted on t_i (stable)
+                LOR_LAUNCH("k_pair_rekey", (double)d.m * 16 + (double)d.m * sizeof(CH), s,
+                           hipLaunchKernelGGL(k_pair_rekey<CH>, dim3(g_el), dim3(kBlock), 0, s, t, d, vc, aux, kc));
+                LOR_TRY(radix_sort<uint64_t>(kc, vc, ka, va, d.m, 32, 32 + b, counts, s, &alt));
+                swap_if(alt);
+            }
+            if (vc != (uint32_t *)sa12) {
                 set_error("internal: sorted sample order not in its buffer");
                 return LOR_EINVAL;
             }
             // free now: the other key buffer (2 x m words) and the other value buffer
-            uint32_t *names = reinterpret_cast<uint32_t *>(alt ? k0 : k1);
+            uint32_t *names = reinterpret_cast<uint32_t *>(ka);
             uint32_t *tmp_idx = names + d.m;
-            uint32_t *tmp_val = alt ? v0 : v1;
-            const uint32_t G = scan_groups(d.m);
+            uint32_t *tmp_val = va;
             LOR_LAUNCH("k_name_count", (double)d.m * 8, s,
-                       hipLaunchKernelGGL((k_name_count<CH, uint64_t, false>), dim3(G), dim3(kBlock), 0, s, t, d,
-                                          ks, (const uint32_t *)sa12, G, gcount));
+                       hipLaunchKernelGGL(k_name_count<uint64_t>, dim3(G), dim3(kBlock), 0, s, kc, d.m, G, gcount));
             LOR_TRY(scan_block_totals(gcount, G, hdr + 1, s));
             LOR_LAUNCH("k_name_write", (double)d.m * 12, s,
-                       hipLaunchKernelGGL((k_name_write<CH, uint64_t, false>), dim3(G), dim3(kBlock), 0, s, t, d,
-                                          ks, (const uint32_t *)sa12, G, gcount, names));
+                       hipLaunchKernelGGL(k_name_write<uint64_t>, dim3(G), dim3(kBlock), 0, s, kc, d.m, G, gcount,
+                                          names));
             LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, names, 0, d.m, tmp_idx, tmp_val, counts, s));
         }
     } else {
@@ -640,28 +657,13 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
         if (run) {
             bool alt = false;
             uint32_t *kc = k0, *ka = k1, *vc = v0, *va = v1;
-            auto swap_if = [&](bool a) {
-                if (a) { uint32_t *x = kc; kc = ka; ka = x; x = vc; vc = va; va = x; }
-            };
-            if (km == KM_U32) {
-                LOR_LAUNCH("k_sample_keys", (double)d.m * 8 + (double)n * sizeof(CH), s,
-                           hipLaunchKernelGGL((k_sample_keys<CH, uint32_t>), dim3(g_el), dim3(kBlock), 0, s, t, d,
-                                              b, 0, 0, kc, vc));
-                LOR_TRY(radix_sort<uint32_t>(kc, vc, ka, va, d.m, 0, kb, counts, s, &alt));
-                swap_if(alt);
-            } else {
-                // LSD over whole symbols: t_{i+2}, then t_{i+1}, then t_i.
-                LOR_LAUNCH("k_sample_keys", (double)d.m * 8 + (double)d.m * sizeof(CH), s,
-                           hipLaunchKernelGGL((k_sample_keys<CH, uint32_t>), dim3(g_el), dim3(kBlock), 0, s, t, d,
-                                              b, 1, 2, kc, vc));
-                LOR_TRY(radix_sort<uint32_t>(kc, vc, ka, va, d.m, 0, b, counts, s, &alt));
-                swap_if(alt);
-                for (int delta = 1; delta >= 0; --delta) {
-                    LOR_LAUNCH("k_rekey", (double)d.m * 8 + (double)d.m * sizeof(CH), s,
-                               hipLaunchKernelGGL((k_rekey<CH>), dim3(g_el), dim3(kBlock), 0, s, t, d, delta, vc, kc));
-                    LOR_TRY(radix_sort<uint32_t>(kc, vc, ka, va, d.m, 0, b, counts, s, &alt));
-                    swap_if(alt);
-                }
+            LOR_LAUNCH("k_sample_keys", (double)d.m * 8 + (double)n * sizeof(CH), s,
+                       hipLaunchKernelGGL((k_sample_keys<CH, uint32_t>), dim3(g_el), dim3(kBlock), 0, s, t, d, b, 0,
+                                          kc, vc));
+            LOR_TRY(radix_sort<uint32_t>(kc, vc, ka, va, d.m, 0, kb, counts, s, &alt));
+            if (alt) {
+                uint32_t *x = kc; kc = ka; ka = x;
+                x = vc; vc = va; va = x;
             }
             if (vc != (uint32_t *)sa12) {
                 set_error("internal: sorted sample order not in its buffer");
@@ -669,23 +671,12 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
             }
             uint32_t *names = ka, *tmp_idx = va, *tmp_val = aux;
             const uint32_t G = scan_groups(d.m);
-            if (km == KM_U32) {
-                LOR_LAUNCH("k_name_count", (double)d.m * 4, s,
-                           hipLaunchKernelGGL((k_name_count<CH, uint32_t, false>), dim3(G), dim3(kBlock), 0, s, t,
-                                              d, kc, vc, G, gcount));
-                LOR_TRY(scan_block_totals(gcount, G, hdr + 1, s));
-                LOR_LAUNCH("k_name_write", (double)d.m * 8, s,
-                           hipLaunchKernelGGL((k_name_write<CH, uint32_t, false>), dim3(G), dim3(kBlock), 0, s, t,
-                                              d, kc, vc, G, gcount, names));
-            } else {
-                LOR_LAUNCH("k_name_count", (double)d.m * 8, s,
-                           hipLaunchKernelGGL((k_name_count<CH, uint32_t, true>), dim3(G), dim3(kBlock), 0, s, t,
-                                              d, kc, vc, G, gcount));
-                LOR_TRY(scan_block_totals(gcount, G, hdr + 1, s));
-                LOR_LAUNCH("k_name_write", (double)d.m * 12, s,
-                           hipLaunchKernelGGL((k_name_write<CH, uint32_t, true>), dim3(G), dim3(kBlock), 0, s, t,
-                                              d, kc, vc, G, gcount, names));
-            }
+            LOR_LAUNCH("k_name_count", (double)d.m * 4, s,
+                       hipLaunchKernelGGL(k_name_count<uint32_t>, dim3(G), dim3(kBlock), 0, s, kc, d.m, G, gcount));
+            LOR_TRY(scan_block_totals(gcount, G, hdr + 1, s));
+            LOR_LAUNCH("k_name_write", (double)d.m * 8, s,
+                       hipLaunchKernelGGL(k_name_write<uint32_t>, dim3(G), dim3(kBlock), 0, s, kc, d.m, G, gcount,
+                                          names));
             LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, names, 0, d.m, tmp_idx, tmp_val, counts, s));
         }
     }
@@ -707,7 +698,7 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
         unique = (hmax == d.m);
         if (trace_on())
             fprintf(stderr, "[lor] dc3 level %d: n=%u m=%u bits/sym=%d %s passes=%d names=%u%s\n", depth, n, d.m, b,
-                    use_table ? "bitmap-naming" : (km == KM_U32 ? "sort-u32" : km == KM_U64 ? "sort-u64" : "sort-staged"),
+                    use_table ? "bitmap-naming" : (km == KM_U32 ? "sort-u32" : km == KM_U64 ? "sort-u64" : "sort-2stage"),
                     use_table ? 0 : passes, hmax, unique ? " unique" : "");
         if (unique && use_table)
             LOR_LAUNCH("k_sa12_from_names", 12.0 * d.m, s,

@@ -4,11 +4,16 @@
 //
 // The paper answers RMQ through a Cartesian tree, an Euler tour and +-1RMQ.
 // Here the structure is a sparse table: level k holds the minimum of every
-// window of 2^k LCP entries, built level by level from level k-1 (two reads,
-// one write per entry, all streaming), and a query reads two overlapping
-// windows that cover its range. With 288 GB of HBM the table fits next to
+// window of 2^k LCP entries, and a query reads two overlapping windows that
+// cover its range. Levels 1-10 are built five at a time: a workgroup loads a
+// tile of level k0-1 plus the halo the next five levels reach into, and
+// computes and writes those levels from LDS, so level k0-1 is read once for
+// five levels. Higher levels (windows wider than a tile) are built one at a
+// time from level k-1 (two streaming reads, one write per entry). With 288 GB of HBM the table fits next to
 // the 1G-suffix arrays, and every query costs four independent gathers
 // (two ISA entries, two table entries) instead of a pointer walk.
+#include <climits>
+
 #include "lor_internal.hpp"
 
 namespace lor {
@@ -19,6 +24,43 @@ __global__ __launch_bounds__(kBlock) void k_st_level(const int32_t *__restrict__
                                                      uint32_t cnt, int32_t *__restrict__ cur) {
     for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock)
         cur[i] = min(prev[i], prev[i + half]);
+}
+
+constexpr uint32_t kStTile = kBlock * 16;   // outputs per workgroup in fused levels
+constexpr int kStFuse = 5;                  // levels per fused pass
+
+__device__ __forceinline__ uint64_t level_offset_dev(uint64_t n, int level);
+
+// Levels k0 .. k0+nl-1 from level k0-1 (`prev`, prev_count entries) for the
+// outputs [i0, i0 + kStTile) of this workgroup.
+__global__ __launch_bounds__(kBlock) void k_st_fused(const int32_t *__restrict__ prev, uint32_t prev_count,
+                                                     uint32_t n, int k0, int nl, int32_t *__restrict__ table) {
+    extern __shared__ int32_t s_buf[];
+    const uint32_t halo = (1u << (k0 - 1)) * ((1u << nl) - 1u);
+    const uint32_t span = kStTile + halo;
+    int32_t *b0 = s_buf, *b1 = s_buf + span;
+    const uint32_t i0 = blockIdx.x * kStTile;
+    for (uint32_t j = threadIdx.x; j < span; j += kBlock) {
+        const uint32_t i = i0 + j;
+        b0[j] = i < prev_count ? prev[i] : INT_MAX;
+    }
+    __syncthreads();
+    uint32_t valid = span;
+    for (int l = 0; l < nl; ++l) {
+        const int k = k0 + l;
+        const uint32_t half = 1u << (k - 1);
+        valid -= half;
+        for (uint32_t j = threadIdx.x; j < valid; j += kBlock) b1[j] = min(b0[j], b0[j + half]);
+        __syncthreads();
+        const uint32_t count = n - (1u << k) + 1u;
+        int32_t *out = table + level_offset_dev(n, k);
+        for (uint32_t j = threadIdx.x; j < kStTile; j += kBlock) {
+            const uint32_t i = i0 + j;
+            if (i < count) out[i] = b1[j];
+        }
+        int32_t *x = b0; b0 = b1; b1 = x;
+        __syncthreads();
+    }
 }
 
 struct Levels {
@@ -89,8 +131,24 @@ uint64_t rmq_level_offset(uint64_t n, int level) {
 }
 
 lor_status rmq_build_levels(const int32_t *lcp, uint32_t n, int32_t *table, int levels, hipStream_t s) {
-    for (int k = 1; k <= levels; ++k) {
+    int k = 1;
+    while (k <= levels && k <= 2 * kStFuse) {
+        const int nl = min(kStFuse, levels - k + 1);
         const int32_t *prev = k == 1 ? lcp : table + rmq_level_offset(n, k - 1);
+        const uint32_t prev_count = n - (1u << (k - 1)) + 1u;
+        const uint32_t count = n - (1u << k) + 1u;
+        const uint32_t halo = (1u << (k - 1)) * ((1u << nl) - 1u);
+        const size_t lds = 2 * (size_t)(kStTile + halo) * sizeof(int32_t);
+        double bytes = 0;
+        for (int l = 0; l < nl; ++l) bytes += 4.0 * (n - (1u << (k + l)) + 1u);
+        bytes += 4.0 * prev_count;
+        LOR_LAUNCH("k_st_fused", bytes, s,
+                   hipLaunchKernelGGL(k_st_fused, dim3(div_up(count, kStTile)), dim3(kBlock), lds, s, prev,
+                                      prev_count, n, k, nl, table));
+        k += nl;
+    }
+    for (; k <= levels; ++k) {
+        const int32_t *prev = table + rmq_level_offset(n, k - 1);
         int32_t *cur = table + rmq_level_offset(n, k);
         const uint32_t half = 1u << (k - 1);
         const uint32_t cnt = n - (1u << k) + 1u;
