@@ -183,8 +183,9 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1404_3448_amd import lor, synth
+    from paper_1404_3448_amd import autotune, lor, synth
 
+    tuned = autotune.load_tuned_plan()          # the committed plan of this GPU, if any
     num_seqs, seq_len, nq = WORKLOADS[args.workload]
     t0 = time.perf_counter()
     w = synth.long_text(seed=3, num_seqs=num_seqs, seq_len=seq_len, num_queries=nq)
@@ -321,7 +322,8 @@ def main():
         "config": {"workload": f"{num_seqs} x {seq_len}-base noncoding-like sequences (40% GC, tandem repeats), "
                                f"joined N = {N}; SA + LCP + ISA + sparse-table RMQ + {nq} suffix-pair queries + "
                                f"longest overlap",
-                   "num_seqs": num_seqs, "seq_len": seq_len, "joined_length": N, "queries": nq, "seed": 3},
+                   "num_seqs": num_seqs, "seq_len": seq_len, "joined_length": N, "queries": nq, "seed": 3,
+                   "plan": lor.lor_plan_get().as_dict(), "plan_source": "autotuned" if tuned else "default"},
         "sa_lcp_msuffixes_per_s": round(N / (sa_lcp_ms * 1e-3) / 1e6, 3),
         "queries_per_s": round(nq / (stages["queries"] * 1e-3), 1) if stages["queries"] > 0 else None,
         "stages_ms": stages,

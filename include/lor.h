@@ -177,8 +177,9 @@ lor_status lor_longest_overlap(const int32_t *sa, const int32_t *lcp, int64_t n,
  * not exceed 2^31 - 1. out_device: device lor_overlap[num_pairs]; record p
  * has seq_p/seq_q in {0 (A), 1 (B)} and offsets inside those sequences, and
  * equals what lor_longest_overlap reports for the pair alone (length 0 gives
- * -1 for the rest). plan: reserved, must be NULL. A base outside 0..3
- * returns LOR_EALPHABET. Synchronises hip_stream before returning. */
+ * -1 for the rest). plan: NULL (use the process-wide plan) or a lor_plan
+ * for this call only. A base outside 0..3 returns LOR_EALPHABET.
+ * Synchronises hip_stream before returning. */
 size_t lor_longest_overlap_batched_workspace(int64_t total_bases, int32_t num_pairs);
 lor_status lor_longest_overlap_batched(const uint8_t *seqs, const int64_t *offsets, int32_t num_pairs,
                                        const void *plan, lor_overlap *out_device,
@@ -197,6 +198,30 @@ lor_status lor_sort_pairs_u32(uint32_t *keys, uint32_t *vals, int64_t n, int32_t
                               void *ws, size_t ws_bytes, void *hip_stream);
 lor_status lor_sort_pairs_u64(uint64_t *keys, uint32_t *vals, int64_t n, int32_t bit_lo, int32_t bit_hi,
                               void *ws, size_t ws_bytes, void *hip_stream);
+
+/* --------------------------------------------------------------- tuning
+ * Tuning knobs of the kernels, chosen by the autotuner
+ * (paper_1404_3448_amd/autotune.py). A plan changes speed, never results.
+ *   digit_bits       radix digit width, 4..8 (Section IV's radix sort takes
+ *                    one bit per pass; wider digits mean fewer passes)
+ *   radix_items_u32  radix tile = 256 threads x items, 32-bit keys: 8|12|16|24
+ *   radix_items_u64  same for 64-bit keys: 4|8|12|16
+ *   merge_items      Step 3 merge-path tile = 256 x items outputs: 4|8|12
+ *   plcp_steps       PLCP positions per lane, 16..1024
+ * lor_plan_set(NULL) restores the defaults. The process-wide plan is not
+ * synchronised: set it before launching work from several threads. */
+typedef struct {
+    int32_t version;          /* 1 */
+    int32_t digit_bits;
+    int32_t radix_items_u32;
+    int32_t radix_items_u64;
+    int32_t merge_items;
+    int32_t plcp_steps;
+} lor_plan;
+
+void lor_plan_default(lor_plan *out);
+void lor_plan_get(lor_plan *out);
+lor_status lor_plan_set(const lor_plan *plan);
 
 /* --------------------------------------------------------- kernel timing
  * Optional per-kernel timing with HIP events recorded on the launch stream

@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <initializer_list>
 #include <vector>
 
 #include "lor_internal.hpp"
@@ -66,6 +67,27 @@ void drain_pending() {
 }
 }  // namespace
 
+namespace {
+Plan g_plan = {8, 16, 8, 8, 128};
+thread_local const Plan *t_plan = nullptr;
+}  // namespace
+
+const Plan &plan() { return t_plan ? *t_plan : g_plan; }
+
+bool plan_valid(const Plan &p) {
+    auto in = [](int v, std::initializer_list<int> ok) {
+        for (int x : ok)
+            if (v == x) return true;
+        return false;
+    };
+    return p.digit_bits >= 4 && p.digit_bits <= 8 && in(p.items_u32, {8, 12, 16, 24}) &&
+           in(p.items_u64, {4, 8, 12, 16}) && in(p.merge_items, {4, 8, 12}) && p.plcp_steps >= 16 &&
+           p.plcp_steps <= 1024;
+}
+
+void plan_set_global(const Plan &p) { g_plan = p; }
+void plan_set_thread(const Plan *p) { t_plan = p; }
+
 void set_error(const char *fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
@@ -105,6 +127,10 @@ using namespace lor;
 namespace {
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+Plan to_plan(const lor_plan *p) {
+    return Plan{p->digit_bits, p->radix_items_u32, p->radix_items_u64, p->merge_items, p->plcp_steps};
+}
 
 lor_status check_ws(void *ws, size_t ws_bytes, size_t need) {
     if (need && !ws) {
@@ -385,9 +411,18 @@ lor_status lor_longest_overlap_batched(const uint8_t *seqs, const int64_t *offse
         set_error("num_pairs %d outside 1..%u", num_pairs, kMaxPairs);
         return LOR_EINVAL;
     }
-    if (!offsets || !out_device || plan) {
-        set_error("NULL offsets/out_device, or a non-NULL plan");
+    if (!offsets || !out_device) {
+        set_error("NULL offsets or out_device");
         return LOR_EINVAL;
+    }
+    Plan call_plan{};
+    if (plan) {
+        const lor_plan *lp = static_cast<const lor_plan *>(plan);
+        call_plan = to_plan(lp);
+        if (lp->version != 1 || !plan_valid(call_plan)) {
+            set_error("invalid plan");
+            return LOR_EINVAL;
+        }
     }
     if (offsets[0] != 0) {
         set_error("offsets[0] must be 0");
@@ -409,7 +444,11 @@ lor_status lor_longest_overlap_batched(const uint8_t *seqs, const int64_t *offse
         return LOR_EINVAL;
     }
     LOR_TRY(check_ws(ws, ws_bytes, lor_longest_overlap_batched_workspace(total, num_pairs)));
-    return batch_overlap(seqs, offsets, (uint32_t)num_pairs, out_device, ws, ws_bytes, (hipStream_t)hip_stream);
+    if (plan) plan_set_thread(&call_plan);
+    const lor_status st =
+        batch_overlap(seqs, offsets, (uint32_t)num_pairs, out_device, ws, ws_bytes, (hipStream_t)hip_stream);
+    plan_set_thread(nullptr);
+    return st;
 }
 
 size_t lor_sort_pairs_workspace(int64_t n, int32_t key_bytes) {
@@ -425,6 +464,33 @@ lor_status lor_sort_pairs_u32(uint32_t *keys, uint32_t *vals, int64_t n, int32_t
 lor_status lor_sort_pairs_u64(uint64_t *keys, uint32_t *vals, int64_t n, int32_t bit_lo, int32_t bit_hi, void *ws,
                               size_t ws_bytes, void *hip_stream) {
     return sort_pairs<uint64_t>(keys, vals, n, bit_lo, bit_hi, ws, ws_bytes, hip_stream);
+}
+
+void lor_plan_default(lor_plan *out) {
+    if (!out) return;
+    *out = lor_plan{1, 8, 16, 8, 8, 128};
+}
+
+void lor_plan_get(lor_plan *out) {
+    if (!out) return;
+    const Plan &p = plan();
+    *out = lor_plan{1, p.digit_bits, p.items_u32, p.items_u64, p.merge_items, p.plcp_steps};
+}
+
+lor_status lor_plan_set(const lor_plan *p) {
+    if (!p) {
+        lor_plan d;
+        lor_plan_default(&d);
+        plan_set_global(to_plan(&d));
+        return LOR_OK;
+    }
+    const Plan q = to_plan(p);
+    if (p->version != 1 || !plan_valid(q)) {
+        set_error("invalid plan");
+        return LOR_EINVAL;
+    }
+    plan_set_global(q);
+    return LOR_OK;
 }
 
 void lor_timing_enable(int32_t on) { g_timing = on != 0; }

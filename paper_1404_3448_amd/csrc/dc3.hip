@@ -36,8 +36,6 @@ namespace {
 constexpr int kScanItems = 8;                         // consecutive items per thread in scan-emit kernels
 constexpr uint32_t kScanTile = kBlock * kScanItems;
 constexpr uint32_t kMaxScanGroups = 1024;
-constexpr int kMergeItems = 8;
-constexpr uint32_t kMergeTile = kBlock * kMergeItems; // outputs per merge workgroup
 
 struct Dims {
     uint32_t n, n0, n1, n2, m, dummy;
@@ -464,21 +462,22 @@ template <typename CH>
 __global__ __launch_bounds__(kBlock) void k_merge_partition(const Rec<CH> *__restrict__ rec,
                                                             const uint32_t *__restrict__ A, uint32_t nA,
                                                             const int32_t *__restrict__ B, uint32_t nB,
-                                                            Dims d, uint32_t parts,
+                                                            Dims d, uint32_t parts, uint32_t tile,
                                                             uint32_t *__restrict__ split) {
     const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
     if (p > parts) return;
-    const uint64_t diag64 = (uint64_t)p * kMergeTile;
+    const uint64_t diag64 = (uint64_t)p * tile;
     const uint32_t diag = (uint32_t)min<uint64_t>(diag64, (uint64_t)nA + nB);
     split[p] = merge_split<CH>(rec, A, nA, B, nB, d, diag);
 }
 
-template <typename CH>
+template <typename CH, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_merge(const Rec<CH> *__restrict__ rec,
                                                   const uint32_t *__restrict__ A, uint32_t nA,
                                                   const int32_t *__restrict__ B, uint32_t nB, Dims d,
                                                   const uint32_t *__restrict__ split,
                                                   int32_t *__restrict__ sa) {
+    constexpr uint32_t kMergeTile = kBlock * ITEMS;
     __shared__ Key4 s_key[kMergeTile];
     __shared__ uint32_t s_pos[kMergeTile];
     __shared__ int32_t s_out[kMergeTile];
@@ -502,8 +501,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(const Rec<CH> *__restrict__ re
     __syncthreads();
     const Key4 *sA = s_key;
     const Key4 *sB = s_key + na;
-    const uint32_t diag = min(cnt, threadIdx.x * (uint32_t)kMergeItems);
-    const uint32_t dend = min(cnt, diag + (uint32_t)kMergeItems);
+    const uint32_t diag = min(cnt, threadIdx.x * (uint32_t)ITEMS);
+    const uint32_t dend = min(cnt, diag + (uint32_t)ITEMS);
     uint32_t lo = diag > nb ? diag - nb : 0u, hi = min(diag, na);
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
@@ -738,9 +737,11 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     LOR_TAKE(ar, uint32_t, d.n0, vals1);
     LOR_TAKE(ar, uint32_t, radix_counts_words(d.n0) + kMaxScanGroups + 64, counts2);
     uint32_t *gcount2 = counts2 + radix_counts_words(d.n0);
-    const uint32_t parts = div_up(n, kMergeTile);
-    uint32_t *split;
-    LOR_TAKE(ar, uint32_t, (size_t)parts + 1, split);
+    const int mitems = plan().merge_items;
+    const uint32_t mtile = kBlock * (uint32_t)mitems;
+    const uint32_t parts = div_up(n, mtile);
+    uint32_t *split;   // sized for the smallest merge tile, so the workspace does not depend on the plan
+    LOR_TAKE(ar, uint32_t, (size_t)div_up(n, kBlock * 4) + 2, split);
     if (run) {
         const uint32_t G = scan_groups(d.m);
         LOR_LAUNCH("k_ns_count", (double)d.m * 4, s,
@@ -756,10 +757,25 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
         const uint32_t nB = d.m - d.dummy;
         LOR_LAUNCH("k_merge_partition", (double)(parts + 1) * 4, s,
                    hipLaunchKernelGGL(k_merge_partition<CH>, dim3(div_up(parts + 1, kBlock)), dim3(kBlock), 0, s,
-                                      rec, A, d.n0, B, nB, d, parts, split));
-        LOR_LAUNCH("k_merge", (double)n * (4 + 4 + sizeof(Rec<CH>)), s,
-                   hipLaunchKernelGGL(k_merge<CH>, dim3(parts), dim3(kBlock), 0, s, rec, A, d.n0, B, nB, d, split,
-                                      sa));
+                                      rec, A, d.n0, B, nB, d, parts, mtile, split));
+        const double mbytes = (double)n * (4 + 4 + sizeof(Rec<CH>));
+        switch (mitems) {
+            case 4:
+                LOR_LAUNCH("k_merge", mbytes, s,
+                           hipLaunchKernelGGL((k_merge<CH, 4>), dim3(parts), dim3(kBlock), 0, s, rec, A, d.n0, B, nB,
+                                              d, split, sa));
+                break;
+            case 12:
+                LOR_LAUNCH("k_merge", mbytes, s,
+                           hipLaunchKernelGGL((k_merge<CH, 12>), dim3(parts), dim3(kBlock), 0, s, rec, A, d.n0, B, nB,
+                                              d, split, sa));
+                break;
+            default:
+                LOR_LAUNCH("k_merge", mbytes, s,
+                           hipLaunchKernelGGL((k_merge<CH, 8>), dim3(parts), dim3(kBlock), 0, s, rec, A, d.n0, B, nB,
+                                              d, split, sa));
+                break;
+        }
     }
     ar.release(mark_level);
     return LOR_OK;

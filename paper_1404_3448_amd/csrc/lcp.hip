@@ -23,7 +23,6 @@ namespace lor {
 
 namespace {
 
-constexpr uint32_t kPlcpSteps = 128;   // positions per lane; a wave covers 64 * kPlcpSteps
 
 __global__ __launch_bounds__(kBlock) void k_phi_keys(const int32_t *__restrict__ sa, uint32_t n,
                                                      uint64_t *__restrict__ keys) {
@@ -76,13 +75,13 @@ __device__ __forceinline__ uint32_t extend(const CH *__restrict__ t, uint32_t n,
 template <typename CH>
 __global__ __launch_bounds__(kBlock) void k_plcp(const CH *__restrict__ t, uint32_t n,
                                                  const int2 *__restrict__ isa_phi, int32_t *__restrict__ plcp,
-                                                 int32_t *__restrict__ isa_out, int wide) {
-    constexpr uint32_t span = kWave * kPlcpSteps;
+                                                 int32_t *__restrict__ isa_out, int wide, uint32_t steps) {
+    const uint32_t span = kWave * steps;
     const uint32_t waves = (n + span - 1) / span;
     const uint32_t lane = threadIdx.x & 63u;
     for (uint32_t w = (blockIdx.x * kBlock + threadIdx.x) / kWave; w < waves; w += gridDim.x * (kBlock / kWave)) {
         uint32_t h = 0;
-        for (uint32_t k = 0, i = w * span + lane; k < kPlcpSteps && i < n; ++k, i += kWave) {
+        for (uint32_t k = 0, i = w * span + lane; k < steps && i < n; ++k, i += kWave) {
             const int2 q = isa_phi[i];
             isa_out[i] = q.x;
             const int32_t j = q.y;
@@ -124,10 +123,11 @@ lor_status lcp_build_t(const CH *text, uint32_t n, const int32_t *sa, int32_t *l
     LOR_TRY(radix_pass<uint64_t>(keys, nullptr, 0, keys2, vals2, n, 32 + shift, nbits, counts, s));
     LOR_LAUNCH("k_phi_place", (double)n * 20, s,
                hipLaunchKernelGGL(k_phi_place, dim3(xcd_grid(n)), dim3(kBlock), 0, s, keys2, vals2, n, isa_phi));
-    const uint32_t waves = div_up(n, kWave * kPlcpSteps);
+    const uint32_t steps = (uint32_t)plan().plcp_steps;
+    const uint32_t waves = div_up(n, kWave * steps);
     LOR_LAUNCH("k_plcp", (double)n * (16 + sizeof(CH)), s,
                hipLaunchKernelGGL(k_plcp<CH>, dim3(grid_for((uint64_t)waves * kWave)), dim3(kBlock), 0, s, text, n,
-                                  isa_phi, reinterpret_cast<int32_t *>(plcp), isa_w, wide));
+                                  isa_phi, reinterpret_cast<int32_t *>(plcp), isa_w, wide, steps));
     uint32_t *tmp_idx = reinterpret_cast<uint32_t *>(keys2);
     return bucketed_scatter(lcp, n, reinterpret_cast<const uint32_t *>(isa_w), plcp, 0, n, tmp_idx, tmp_idx + n,
                             counts, s);

@@ -82,6 +82,21 @@ constexpr size_t kHeaderBytes = 256;
 // Device count of compute units (queried once per device).
 int num_cus();
 
+// ------------------------------------------------------------------ plan
+// Tuning knobs chosen by the autotuner. A plan changes speed, never results.
+struct Plan {
+    int digit_bits;     // radix digit width, 4..8
+    int items_u32;      // radix items per thread, 32-bit keys: 8, 12, 16, 24
+    int items_u64;      // radix items per thread, 64-bit keys: 4, 8, 12, 16
+    int merge_items;    // merge outputs per thread: 4, 8, 12
+    int plcp_steps;     // PLCP positions per lane: 32..512
+};
+const Plan &plan();                 // the calling thread's plan
+bool plan_valid(const Plan &p);
+void plan_set_global(const Plan &p);
+// Per-call override for the calling thread (nullptr clears it).
+void plan_set_thread(const Plan *p);
+
 // -------------------------------------------------------- kernel timing
 // Timing is keyed by kernel name, so the figures line up with a profiler's.
 bool timing_on();

@@ -3,7 +3,8 @@
 // Section IV sorts DC3's sample and non-sample keys with a radix sort that
 // walks the digits from least to most significant, each pass a stable split
 // computed with a prefix scan (one bit per pass in the paper's kernel).
-// Here a pass handles an 8-bit digit and runs as three kernels:
+// Here a pass handles a digit of up to 8 bits (the width and the tile size
+// come from the tuning plan) and runs as three kernels:
 //   1. count  : every workgroup owns a contiguous run of tiles and builds the
 //               digit histogram of its run in LDS (per-wave sub-histograms);
 //   2. scan   : a device-wide exclusive scan turns the digit-major table
@@ -27,9 +28,6 @@ constexpr int kDigitBits = 8;
 constexpr int kBins = 1 << kDigitBits;
 constexpr uint32_t kMaxGroups = 1024;     // workgroups per pass (fixed: workspace sizes are device-independent)
 
-template <typename K> struct RadixCfg;
-template <> struct RadixCfg<uint32_t> { static constexpr int kItems = 16; };
-template <> struct RadixCfg<uint64_t> { static constexpr int kItems = 8; };
 
 __device__ __forceinline__ void tile_range(uint32_t tiles, uint32_t groups, uint32_t g, uint32_t *t0,
                                            uint32_t *t1) {
@@ -245,11 +243,25 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t *__restrict__ dat
     }
 }
 
-template <typename K>
-uint32_t groups_for(uint32_t n, uint32_t *tiles) {
-    constexpr uint32_t TILE = kBlock * RadixCfg<K>::kItems;
-    *tiles = div_up(n, TILE);
+uint32_t groups_for(uint32_t n, uint32_t tile, uint32_t *tiles) {
+    *tiles = div_up(n, tile);
     return *tiles < kMaxGroups ? (*tiles ? *tiles : 1) : kMaxGroups;
+}
+
+template <typename K, int ITEMS>
+lor_status radix_pass_items(const K *ki, const uint32_t *vi, uint32_t voff, K *ko, uint32_t *vo, uint32_t n,
+                            int shift, int nbits, uint32_t *counts, hipStream_t s) {
+    uint32_t tiles;
+    const uint32_t groups = groups_for(n, kBlock * ITEMS, &tiles);
+    const uint32_t mask = (1u << nbits) - 1u;
+    LOR_LAUNCH("k_radix_count", (double)n * sizeof(K), s,
+               hipLaunchKernelGGL((k_radix_count<K, ITEMS>), dim3(groups), dim3(kBlock), 0, s, ki, n, tiles, groups,
+                                  shift, mask, counts));
+    LOR_TRY(scan_exclusive(counts, (uint32_t)kBins * groups, counts + (size_t)kBins * kMaxGroups, nullptr, s));
+    LOR_LAUNCH("k_radix_scatter", (double)n * ((vi ? 2.0 : 1.0) * (sizeof(K) + 4) + (vi ? 0.0 : sizeof(K))), s,
+               hipLaunchKernelGGL((k_radix_scatter<K, ITEMS>), dim3(groups), dim3(kBlock), 0, s, ki, vi, ko, vo, n,
+                                  tiles, groups, shift, nbits, counts, voff));
+    return LOR_OK;
 }
 
 }  // namespace
@@ -270,7 +282,8 @@ lor_status scan_exclusive(uint32_t *data, uint32_t count, uint32_t *tmp, uint32_
 }
 
 int radix_passes(int bit_lo, int bit_hi) {
-    return bit_hi > bit_lo ? (bit_hi - bit_lo + kDigitBits - 1) / kDigitBits : 0;
+    const int step = plan().digit_bits;
+    return bit_hi > bit_lo ? (bit_hi - bit_lo + step - 1) / step : 0;
 }
 
 lor_status scan_block_totals(uint32_t *vals, uint32_t count, uint32_t *total, hipStream_t s) {
@@ -282,19 +295,23 @@ lor_status scan_block_totals(uint32_t *vals, uint32_t count, uint32_t *total, hi
 template <typename K>
 lor_status radix_pass(const K *ki, const uint32_t *vi, uint32_t voff, K *ko, uint32_t *vo, uint32_t n, int shift,
                       int nbits, uint32_t *counts, hipStream_t s) {
-    constexpr int ITEMS = RadixCfg<K>::kItems;
     if (n == 0) return LOR_OK;
-    uint32_t tiles;
-    const uint32_t groups = groups_for<K>(n, &tiles);
-    const uint32_t mask = (1u << nbits) - 1u;
-    LOR_LAUNCH("k_radix_count", (double)n * sizeof(K), s,
-               hipLaunchKernelGGL((k_radix_count<K, ITEMS>), dim3(groups), dim3(kBlock), 0, s, ki, n, tiles, groups,
-                                  shift, mask, counts));
-    LOR_TRY(scan_exclusive(counts, (uint32_t)kBins * groups, counts + (size_t)kBins * kMaxGroups, nullptr, s));
-    LOR_LAUNCH("k_radix_scatter", (double)n * ((vi ? 2.0 : 1.0) * (sizeof(K) + 4) + (vi ? 0.0 : sizeof(K))), s,
-               hipLaunchKernelGGL((k_radix_scatter<K, ITEMS>), dim3(groups), dim3(kBlock), 0, s, ki, vi, ko, vo, n,
-                                  tiles, groups, shift, nbits, counts, voff));
-    return LOR_OK;
+    const int items = sizeof(K) == 4 ? plan().items_u32 : plan().items_u64;
+    if constexpr (sizeof(K) == 4) {
+        switch (items) {
+            case 8: return radix_pass_items<K, 8>(ki, vi, voff, ko, vo, n, shift, nbits, counts, s);
+            case 12: return radix_pass_items<K, 12>(ki, vi, voff, ko, vo, n, shift, nbits, counts, s);
+            case 24: return radix_pass_items<K, 24>(ki, vi, voff, ko, vo, n, shift, nbits, counts, s);
+            default: return radix_pass_items<K, 16>(ki, vi, voff, ko, vo, n, shift, nbits, counts, s);
+        }
+    } else {
+        switch (items) {
+            case 4: return radix_pass_items<K, 4>(ki, vi, voff, ko, vo, n, shift, nbits, counts, s);
+            case 12: return radix_pass_items<K, 12>(ki, vi, voff, ko, vo, n, shift, nbits, counts, s);
+            case 16: return radix_pass_items<K, 16>(ki, vi, voff, ko, vo, n, shift, nbits, counts, s);
+            default: return radix_pass_items<K, 8>(ki, vi, voff, ko, vo, n, shift, nbits, counts, s);
+        }
+    }
 }
 
 template <typename K>
@@ -304,8 +321,9 @@ lor_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, uint32_t n, int 
     if (n <= 1 || bit_hi <= bit_lo) return LOR_OK;
     K *ki = k0, *ko = k1;
     uint32_t *vi = v0, *vo = v1;
-    for (int shift = bit_lo; shift < bit_hi; shift += kDigitBits) {
-        const int nbits = min(kDigitBits, bit_hi - shift);
+    const int step = plan().digit_bits;
+    for (int shift = bit_lo; shift < bit_hi; shift += step) {
+        const int nbits = min(step, bit_hi - shift);
         LOR_TRY(radix_pass<K>(ki, vi, 0, ko, vo, n, shift, nbits, counts, s));
         K *tk = ki; ki = ko; ko = tk;
         uint32_t *tv = vi; vi = vo; vo = tv;

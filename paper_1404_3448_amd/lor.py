@@ -44,6 +44,14 @@ class lor_overlap(ctypes.Structure):
                 ("off_p", ctypes.c_int64), ("off_q", ctypes.c_int64)]
 
 
+class lor_plan(ctypes.Structure):
+    _fields_ = [("version", ctypes.c_int32), ("digit_bits", ctypes.c_int32), ("radix_items_u32", ctypes.c_int32),
+                ("radix_items_u64", ctypes.c_int32), ("merge_items", ctypes.c_int32), ("plcp_steps", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
 class lor_timing(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
                 ("bytes", ctypes.c_double)]
@@ -88,6 +96,9 @@ def lib():
         "lor_sort_pairs_workspace": ([I64, I32], SZ),
         "lor_sort_pairs_u32": ([P, P, I64, I32, I32, P, SZ, P], I32),
         "lor_sort_pairs_u64": ([P, P, I64, I32, I32, P, SZ, P], I32),
+        "lor_plan_default": ([ctypes.POINTER(lor_plan)], None),
+        "lor_plan_get": ([ctypes.POINTER(lor_plan)], None),
+        "lor_plan_set": ([ctypes.POINTER(lor_plan)], I32),
         "lor_timing_enable": ([I32], None),
         "lor_timing_reset": ([], None),
         "lor_timing_read": ([ctypes.POINTER(lor_timing), I32], I32),
@@ -298,7 +309,7 @@ def lor_longest_overlap_batched_workspace(total_bases: int, num_pairs: int) -> i
     return int(lib().lor_longest_overlap_batched_workspace(total_bases, num_pairs))
 
 
-def lor_longest_overlap_batched(seqs, offsets, out=None, ws=None, stream=None):
+def lor_longest_overlap_batched(seqs, offsets, out=None, ws=None, stream=None, plan=None):
     """Longest overlap of every pair (sequences 2p, 2p+1). Returns an int64
     device tensor [num_pairs, 4] of (length, off_p, off_q, seq_p | seq_q << 8)
     views of the lor_overlap records (see records_to_tuples)."""
@@ -312,7 +323,10 @@ def lor_longest_overlap_batched(seqs, offsets, out=None, ws=None, stream=None):
         out = torch.empty(P * ctypes.sizeof(lor_overlap), dtype=torch.uint8, device=seqs.device)
     nbytes = lor_longest_overlap_batched_workspace(int(o[-1]), P)
     ws = _workspace(nbytes, seqs.device, ws)
-    st = lib().lor_longest_overlap_batched(_ptr(seqs), o.ctypes.data_as(ctypes.c_void_p), P, None, _ptr(out),
+    pl = None
+    if plan is not None:
+        pl = ctypes.byref(plan if isinstance(plan, lor_plan) else make_plan(**plan))
+    st = lib().lor_longest_overlap_batched(_ptr(seqs), o.ctypes.data_as(ctypes.c_void_p), P, pl, _ptr(out),
                                            _ptr(ws), ws.numel() * ws.element_size(), _stream(stream))
     _check("lor_longest_overlap_batched", st)
     return out
@@ -353,6 +367,37 @@ def lor_sort_pairs_u32(keys, vals, bit_lo=0, bit_hi=32, ws=None, stream=None):
 def lor_sort_pairs_u64(keys, vals, bit_lo=0, bit_hi=64, ws=None, stream=None):
     """Stable in-place sort of (keys: int64 bits, vals: int32) by key bits [bit_lo, bit_hi)."""
     return _sort_pairs("lor_sort_pairs_u64", 8, keys, vals, bit_lo, bit_hi, ws, stream)
+
+
+# ----------------------------------------------------------------- plans
+
+def lor_plan_default() -> lor_plan:
+    p = lor_plan()
+    lib().lor_plan_default(ctypes.byref(p))
+    return p
+
+
+def lor_plan_get() -> lor_plan:
+    p = lor_plan()
+    lib().lor_plan_get(ctypes.byref(p))
+    return p
+
+
+def lor_plan_set(plan=None):
+    """Set the process-wide plan (a lor_plan, a dict of its fields, or None for the defaults)."""
+    if plan is None:
+        _check("lor_plan_set", lib().lor_plan_set(None))
+        return
+    p = plan if isinstance(plan, lor_plan) else make_plan(**plan)
+    _check("lor_plan_set", lib().lor_plan_set(ctypes.byref(p)))
+
+
+def make_plan(**fields) -> lor_plan:
+    p = lor_plan_default()
+    for k, v in fields.items():
+        if k != "version":
+            setattr(p, k, int(v))
+    return p
 
 
 # ----------------------------------------------------------------- timing

@@ -93,3 +93,20 @@ def test_size_queries():
     assert lor.lor_build_sa_workspace((1 << 31), 2) == 0
     assert lor.lor_build_lcp_workspace(1000) >= 4000
     assert lor.lor_sort_pairs_workspace(1000, 3) == 0
+
+
+def test_plan_validation():
+    assert lor.lor_plan_get().as_dict() == lor.lor_plan_default().as_dict()
+    lor.lor_plan_set({"digit_bits": 6, "merge_items": 4})
+    assert lor.lor_plan_get().digit_bits == 6
+    for bad in ({"digit_bits": 9}, {"radix_items_u32": 10}, {"radix_items_u64": 24}, {"merge_items": 16},
+                {"plcp_steps": 4}):
+        with pytest.raises(lor.LorError):
+            lor.lor_plan_set(bad)
+    lor.lor_plan_set(None)
+    assert lor.lor_plan_get().as_dict() == lor.lor_plan_default().as_dict()
+    # workspace sizes do not depend on the plan
+    a = lor.lor_build_sa_workspace(1 << 20, 2)
+    lor.lor_plan_set({"merge_items": 4, "digit_bits": 4})
+    assert lor.lor_build_sa_workspace(1 << 20, 2) == a
+    lor.lor_plan_set(None)
