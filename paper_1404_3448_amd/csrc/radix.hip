@@ -92,6 +92,22 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const K *__restrict__ 
     uint32_t t0, t1;
     tile_range(tiles, groups, blockIdx.x, &t0, &t1);
 
+    // The next tile's keys and values are loaded while the current tile is
+    // ranked and stored, so global-memory latency overlaps the LDS work.
+    K kn[ITEMS];
+    uint32_t vn[ITEMS];
+    auto load_tile = [&](uint32_t t) {
+        const uint32_t first = t * TILE + w * (kWave * ITEMS) + lane;
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const uint32_t e = first + r * kWave;
+            const bool ok = e < n;
+            kn[r] = ok ? kin[e] : K(0);
+            vn[r] = ok ? (vin ? vin[e] : e + voff) : 0u;
+        }
+    };
+    if (t0 < t1) load_tile(t0);
+
     for (uint32_t t = t0; t < t1; ++t) {
         const uint32_t base = t * TILE;
         const uint32_t nvalid = min(TILE, n - base);
@@ -105,11 +121,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const K *__restrict__ 
         uint32_t rk[ITEMS];
 #pragma unroll
         for (int r = 0; r < ITEMS; ++r) {
-            uint32_t e = wfirst + r * kWave;
-            bool ok = e < n;
-            k[r] = ok ? kin[e] : K(0);
-            v[r] = ok ? (vin ? vin[e] : e + voff) : 0u;
+            k[r] = kn[r];
+            v[r] = vn[r];
         }
+        if (t + 1 < t1) load_tile(t + 1);
 #pragma unroll
         for (int r = 0; r < ITEMS; ++r) {
             const bool ok = (wfirst + r * kWave) < n;
