@@ -189,7 +189,8 @@ lor_status lor_longest_overlap_batched(const uint8_t *seqs, const int64_t *offse
  * Stable LSD radix sort of (key, value) pairs by key bits [bit_lo, bit_hi)
  * (Section IV: radix sort from the least to the most significant digit, the
  * sort DC3 uses for sample and non-sample suffixes). Digits of up to 8 bits
- * are ranked per tile with wavefront ballots and scattered through LDS.
+ * are ranked per tile from per-wave lane masks built in LDS and scattered
+ * through LDS.
  * keys/vals: device arrays of n entries, sorted in place (the workspace holds
  * the second buffers). 0 <= bit_lo < bit_hi <= 32 (u32) or 64 (u64).
  * ws: at least lor_sort_pairs_workspace(n, key_bytes) bytes (key_bytes 4|8). */
@@ -205,7 +206,7 @@ lor_status lor_sort_pairs_u64(uint64_t *keys, uint32_t *vals, int64_t n, int32_t
  *   digit_bits       radix digit width, 4..8 (Section IV's radix sort takes
  *                    one bit per pass; wider digits mean fewer passes)
  *   radix_items_u32  radix tile = 256 threads x items, 32-bit keys: 8|12|16|24
- *   radix_items_u64  same for 64-bit keys: 4|8|12|16
+ *   radix_items_u64  same for 64-bit keys: 8|12|16
  *   merge_items      Step 3 merge-path tile = 256 x items outputs: 4|8|12
  *   plcp_steps       PLCP positions per lane, 16..1024
  * lor_plan_set(NULL) restores the defaults. The process-wide plan is not

@@ -102,7 +102,7 @@ def tune(log=print) -> dict:
         vv.copy_(v64)
         lor.lor_sort_pairs_u64(kk, vv, 0, 58, ws=ws64)
 
-    for items in (4, 8, 12, 16):
+    for items in (8, 12, 16):
         lor.lor_plan_set(dict(best, radix_items_u64=items))
         t = _time(sort64)
         meas[f"sort_u64 items={items}"] = t

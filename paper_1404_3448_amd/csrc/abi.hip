@@ -81,7 +81,7 @@ bool plan_valid(const Plan &p) {
         return false;
     };
     return p.digit_bits >= 4 && p.digit_bits <= 8 && in(p.items_u32, {8, 12, 16, 24}) &&
-           in(p.items_u64, {4, 8, 12, 16}) && in(p.merge_items, {4, 8, 12}) && p.plcp_steps >= 16 &&
+           in(p.items_u64, {8, 12, 16}) && in(p.merge_items, {4, 8, 12}) && p.plcp_steps >= 16 &&
            p.plcp_steps <= 1024;
 }
 

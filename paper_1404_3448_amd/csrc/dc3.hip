@@ -638,21 +638,23 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
             }
             // free now: the other key buffer (2 x m words) and the other value buffer
             uint32_t *names = reinterpret_cast<uint32_t *>(ka);
-            uint32_t *tmp_idx = names + d.m;
-            uint32_t *tmp_val = va;
+            // scatter buffers: the rest of ka, va, and kc once the names are out
+            uint32_t *const tmp4[4] = {names + d.m, va, reinterpret_cast<uint32_t *>(kc),
+                                       reinterpret_cast<uint32_t *>(kc) + d.m};
             LOR_LAUNCH("k_name_count", (double)d.m * 8, s,
                        hipLaunchKernelGGL(k_name_count<uint64_t>, dim3(G), dim3(kBlock), 0, s, kc, d.m, G, gcount));
             LOR_TRY(scan_block_totals(gcount, G, hdr + 1, s));
             LOR_LAUNCH("k_name_write", (double)d.m * 12, s,
                        hipLaunchKernelGGL(k_name_write<uint64_t>, dim3(G), dim3(kBlock), 0, s, kc, d.m, G, gcount,
                                           names));
-            LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, names, 0, d.m, tmp_idx, tmp_val, counts, s));
+            LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, names, 0, d.m, tmp4, counts, s));
         }
     } else {
-        uint32_t *k0, *k1, *aux;
+        uint32_t *k0, *k1, *aux, *aux2;
         LOR_TAKE(ar, uint32_t, d.m, k0);
         LOR_TAKE(ar, uint32_t, d.m, k1);
         LOR_TAKE(ar, uint32_t, d.m, aux);
+        LOR_TAKE(ar, uint32_t, d.m, aux2);
         if (run) {
             bool alt = false;
             uint32_t *kc = k0, *ka = k1, *vc = v0, *va = v1;
@@ -668,7 +670,8 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
                 set_error("internal: sorted sample order not in its buffer");
                 return LOR_EINVAL;
             }
-            uint32_t *names = ka, *tmp_idx = va, *tmp_val = aux;
+            uint32_t *names = ka;
+            uint32_t *const tmp4[4] = {va, aux, aux2, kc};   // kc is free once the names are out
             const uint32_t G = scan_groups(d.m);
             LOR_LAUNCH("k_name_count", (double)d.m * 4, s,
                        hipLaunchKernelGGL(k_name_count<uint32_t>, dim3(G), dim3(kBlock), 0, s, kc, d.m, G, gcount));
@@ -676,7 +679,7 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
             LOR_LAUNCH("k_name_write", (double)d.m * 8, s,
                        hipLaunchKernelGGL(k_name_write<uint32_t>, dim3(G), dim3(kBlock), 0, s, kc, d.m, G, gcount,
                                           names));
-            LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, names, 0, d.m, tmp_idx, tmp_val, counts, s));
+            LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, names, 0, d.m, tmp4, counts, s));
         }
     }
 
@@ -712,11 +715,10 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
         LOR_TRY(dc3_level<int32_t>(R, d.m, hmax, sa12, ar, hdr, s, depth + 1));
         // rank12[sa12[r]] = r + 1, as a bucketed scatter
         const size_t mk = ar.mark();
-        uint32_t *ta, *tb, *cr;
-        LOR_TAKE(ar, uint32_t, d.m, ta);
-        LOR_TAKE(ar, uint32_t, d.m, tb);
+        uint32_t *tb[4], *cr;
+        for (int i = 0; i < 4; ++i) LOR_TAKE(ar, uint32_t, d.m, tb[i]);
         LOR_TAKE(ar, uint32_t, radix_counts_words(d.m), cr);
-        if (run) LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, nullptr, 1, d.m, ta, tb, cr, s));
+        if (run) LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, nullptr, 1, d.m, tb, cr, s));
         ar.release(mk);
     }
     const int32_t *rank12 = R;

@@ -4,9 +4,10 @@
 // Permuted-LCP method:
 //   phi    : for every rank r, the pair (r, SA[r-1]) goes to text position
 //            SA[r] -- the inverse permutation and Phi together. The pairs
-//            travel as 64-bit keys (SA[r] << 32 | SA[r-1]) through one radix
-//            pass on the top bits of SA[r], then are stored bucket by bucket
-//            (see scatter.hip for why bucketing beats a random scatter);
+//            travel as 64-bit keys (SA[r] << 32 | SA[r-1]) through radix
+//            passes on the top 16 bits of SA[r], then are stored bucket by
+//            bucket (see scatter.hip for why bucketing beats a random
+//            scatter);
 //   plcp   : PLCP[i] = lcp(suffix i, suffix Phi[i]). Kasai's bound
 //            PLCP[i+1] >= PLCP[i] - 1 iterates to PLCP[i+d] >= PLCP[i] - d.
 //            A wave owns a run of 64*K consecutive positions; lane l takes
@@ -113,24 +114,39 @@ lor_status lcp_build_t(const CH *text, uint32_t n, const int32_t *sa, int32_t *l
     LOR_TAKE(ar, uint32_t, n, isa_tmp);
     LOR_TAKE(ar, uint32_t, radix_counts_words(n), counts);
     if (n == 0) return LOR_OK;
-    int2 *isa_phi = reinterpret_cast<int2 *>(keys);
     int32_t *isa_w = isa ? isa : reinterpret_cast<int32_t *>(isa_tmp);
     const int wide = ((uintptr_t)text % 8) == 0;
-    int shift, nbits;
-    bucket_digit(n, &shift, &nbits);
     LOR_LAUNCH("k_phi_keys", (double)n * 12, s,
                hipLaunchKernelGGL(k_phi_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, sa, n, keys));
-    LOR_TRY(radix_pass<uint64_t>(keys, nullptr, 0, keys2, vals2, n, 32 + shift, nbits, counts, s));
+    // Bucket the pairs by the top bits of SA[r] (two passes for large n);
+    // the (ISA, Phi) pairs then go to whichever 8-byte buffer is free.
+    const BucketDigits g = bucket_digits(n);
+    const uint64_t *bk;
+    const uint32_t *bv;
+    int2 *isa_phi;
+    if (g.lo_bits > 0) {
+        LOR_TRY(radix_pass<uint64_t>(keys, nullptr, 0, keys2, vals2, n, 32 + g.lo_shift, g.lo_bits, counts, s));
+        LOR_TRY(radix_pass<uint64_t>(keys2, vals2, 0, keys, plcp, n, 32 + g.hi_shift, g.hi_bits, counts, s));
+        bk = keys;
+        bv = plcp;
+        isa_phi = reinterpret_cast<int2 *>(keys2);
+    } else {
+        LOR_TRY(radix_pass<uint64_t>(keys, nullptr, 0, keys2, vals2, n, 32 + g.hi_shift, g.hi_bits, counts, s));
+        bk = keys2;
+        bv = vals2;
+        isa_phi = reinterpret_cast<int2 *>(keys);
+    }
     LOR_LAUNCH("k_phi_place", (double)n * 20, s,
-               hipLaunchKernelGGL(k_phi_place, dim3(xcd_grid(n)), dim3(kBlock), 0, s, keys2, vals2, n, isa_phi));
+               hipLaunchKernelGGL(k_phi_place, dim3(xcd_grid(n)), dim3(kBlock), 0, s, bk, bv, n, isa_phi));
     const uint32_t steps = (uint32_t)plan().plcp_steps;
     const uint32_t waves = div_up(n, kWave * steps);
     LOR_LAUNCH("k_plcp", (double)n * (16 + sizeof(CH)), s,
                hipLaunchKernelGGL(k_plcp<CH>, dim3(grid_for((uint64_t)waves * kWave)), dim3(kBlock), 0, s, text, n,
                                   isa_phi, reinterpret_cast<int32_t *>(plcp), isa_w, wide, steps));
-    uint32_t *tmp_idx = reinterpret_cast<uint32_t *>(keys2);
-    return bucketed_scatter(lcp, n, reinterpret_cast<const uint32_t *>(isa_w), plcp, 0, n, tmp_idx, tmp_idx + n,
-                            counts, s);
+    // both 8-byte buffers are free again: four n-word scatter buffers
+    uint32_t *k32 = reinterpret_cast<uint32_t *>(keys), *k232 = reinterpret_cast<uint32_t *>(keys2);
+    uint32_t *const tmp4[4] = {k32, k32 + n, k232, k232 + n};
+    return bucketed_scatter(lcp, n, reinterpret_cast<const uint32_t *>(isa_w), plcp, 0, n, tmp4, counts, s);
 }
 
 lor_status lcp_build(const uint8_t *text, uint32_t n, const int32_t *sa, int32_t *lcp, int32_t *isa, Arena &ar,

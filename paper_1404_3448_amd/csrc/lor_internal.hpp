@@ -160,15 +160,19 @@ int radix_passes(int bit_lo, int bit_hi);
 
 // ------------------------------------------------------ bucketed scatter
 // dst[idx[i]] = val[i] for i < n (idx a permutation into dst[0..dst_n) or a
-// subset of it): one radix pass partitions the pairs by the top 8 bits of
-// idx, then a second kernel stores them bucket by bucket, so stores to one
-// range of dst are close in time and combine in L2 / the Infinity Cache
-// instead of each costing a line of HBM traffic. val == nullptr stands for
-// values i + voff. tmp_idx/tmp_val: n words each; counts: radix_counts_words.
+// subset of it): stable radix passes partition the pairs by the top (up to
+// 16) bits of idx, then a last kernel stores them bucket by bucket, so stores
+// to one range of dst are close in time and combine in L2 instead of each
+// costing a line of HBM traffic. val == nullptr stands for values i + voff.
+// tmp: four buffers of n words (the last two are unused when dst_n needs at
+// most 8 index bits); counts: radix_counts_words(n).
+struct BucketDigits {
+    int hi_shift, hi_bits;   // top digit of an index
+    int lo_shift, lo_bits;   // the digit below it (lo_bits == 0: none)
+};
+BucketDigits bucket_digits(uint32_t dst_n);
 lor_status bucketed_scatter(int32_t *dst, uint32_t dst_n, const uint32_t *idx, const uint32_t *val, uint32_t voff,
-                            uint32_t n, uint32_t *tmp_idx, uint32_t *tmp_val, uint32_t *counts, hipStream_t s);
-// Digit (shift, nbits <= 8) that splits 0..dst_n-1 into at most 256 slices.
-void bucket_digit(uint32_t dst_n, int *shift, int *nbits);
+                            uint32_t n, uint32_t *const tmp[4], uint32_t *counts, hipStream_t s);
 
 // ------------------------------------------------------------- device scan
 // Exclusive scan of `count` u32 block totals in place (one workgroup);

@@ -4,20 +4,29 @@
 // walks the digits from least to most significant, each pass a stable split
 // computed with a prefix scan (one bit per pass in the paper's kernel).
 // Here a pass handles a digit of up to 8 bits (the width and the tile size
-// come from the tuning plan) and runs as three kernels:
-//   1. count  : every workgroup owns a contiguous run of tiles and builds the
-//               digit histogram of its run in LDS (per-wave sub-histograms);
-//   2. scan   : a device-wide exclusive scan turns the digit-major table
-//               counts[d][g] into global offsets (digit d of group g starts
-//               after every smaller digit and after digit d of groups < g);
-//   3. scatter: every workgroup walks its tiles in order; inside a tile each
-//               wave ranks its elements by digit with 8 ballots per round
-//               (lanes with the same digit form a peer mask; the rank is the
-//               number of peers in lower lanes), the tile is reordered by
-//               digit in LDS, and written out so that runs of equal digits
-//               leave as contiguous stores.
-// Element order inside a tile is wave-major then round-major then lane, so
-// ranks follow input order and every pass is stable.
+// come from the tuning plan) and runs as follows, one workgroup per tile:
+//   1. count  : the digit histogram of every tile, built in LDS (one
+//               sub-histogram per wave) and stored tile-major;
+//   2. scan   : a column scan of the tile-major table gives every (tile,
+//               digit) its output offset: all smaller digits first, then
+//               digit d of the earlier tiles;
+//   3. scatter: each wave ranks its elements by digit (below), the tile is
+//               reordered by digit in LDS and written out, so runs of equal
+//               digits leave as contiguous stores.
+// Ranking without ballots: for every item, each lane ORs its lane bit into
+// its wave's 64-bit word for its digit in LDS, reads the word back (the
+// wave's LDS instructions run in order, so the word then holds exactly the
+// lanes of this item with that digit) and clears it. The rank is the number
+// of those lanes below the calling lane plus the wave's running count for
+// the digit, which the lowest of them advances.
+// Element order inside a tile is wave-major, then item, then lane, so ranks
+// follow input order and every pass is stable.
+//
+// Tiles are dealt to the 8 XCDs in contiguous eighths of the array (tile
+// order inside each eighth follows the workgroup index). The tiles in flight
+// on one XCD are then neighbours, their runs of a digit are adjacent in the
+// output, and the cache lines the runs share are completed in that XCD's L2
+// instead of leaving it part-written.
 #include "lor_internal.hpp"
 
 namespace lor {
@@ -26,156 +35,229 @@ namespace {
 
 constexpr int kDigitBits = 8;
 constexpr int kBins = 1 << kDigitBits;
-constexpr uint32_t kMaxGroups = 1024;     // workgroups per pass (fixed: workspace sizes are device-independent)
+constexpr uint32_t kMinTile = kBlock * 8;   // smallest tile of any plan (sizes the count table)
+constexpr uint32_t kColChunks = 256;        // row chunks of the column scan
 
-
-__device__ __forceinline__ void tile_range(uint32_t tiles, uint32_t groups, uint32_t g, uint32_t *t0,
-                                           uint32_t *t1) {
-    *t0 = (uint32_t)((uint64_t)tiles * g / groups);
-    *t1 = (uint32_t)((uint64_t)tiles * (g + 1) / groups);
+// Tile handled by this workgroup: XCD x = blockIdx mod 8 takes the x-th
+// eighth of the tiles, in workgroup order. Returns false for the padding
+// workgroups of the last eighth.
+__device__ __forceinline__ bool xcd_tile(uint32_t tiles, uint32_t *tile) {
+    const uint32_t per = (tiles + kXcds - 1) / kXcds;
+    const uint32_t x = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
+    *tile = x * per + j;
+    return j < per && *tile < tiles;
 }
 
+inline uint32_t xcd_tile_grid(uint32_t tiles) { return kXcds * ((tiles + kXcds - 1) / kXcds); }
+
 template <typename K, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_radix_count(const K *__restrict__ keys, uint32_t n,
-                                                        uint32_t tiles, uint32_t groups, int shift,
-                                                        uint32_t mask, uint32_t *__restrict__ counts) {
+__global__ __launch_bounds__(kBlock) void k_radix_count(const K *__restrict__ keys, uint32_t n, uint32_t tiles,
+                                                        int shift, uint32_t mask, uint32_t *__restrict__ table) {
     constexpr uint32_t TILE = kBlock * ITEMS;
     __shared__ uint32_t hist[kBlock / kWave][kBins];
     const unsigned tid = threadIdx.x, w = tid >> 6;
+    uint32_t t;
+    if (!xcd_tile(tiles, &t)) return;
 #pragma unroll
     for (int i = 0; i < kBlock / kWave; ++i) hist[i][tid] = 0;
     __syncthreads();
-    uint32_t t0, t1;
-    tile_range(tiles, groups, blockIdx.x, &t0, &t1);
-    for (uint32_t t = t0; t < t1; ++t) {
-        const uint32_t base = t * TILE + tid;
-        K k[ITEMS];
+    const uint32_t base = t * TILE + tid;
+    K k[ITEMS];
 #pragma unroll
-        for (int r = 0; r < ITEMS; ++r) {
-            uint32_t e = base + r * kBlock;
-            k[r] = (e < n) ? keys[e] : K(0);
-        }
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t e = base + r * kBlock;
+        k[r] = (e < n) ? keys[e] : K(0);
+    }
 #pragma unroll
-        for (int r = 0; r < ITEMS; ++r) {
-            uint32_t e = base + r * kBlock;
-            if (e < n) atomicAdd(&hist[w][(uint32_t)(k[r] >> shift) & mask], 1u);
-        }
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t e = base + r * kBlock;
+        if (e < n) atomicAdd(&hist[w][(uint32_t)(k[r] >> shift) & mask], 1u);
     }
     __syncthreads();
-    uint32_t s = 0;
+    uint32_t c = 0;
 #pragma unroll
-    for (int i = 0; i < kBlock / kWave; ++i) s += hist[i][tid];
-    counts[(size_t)tid * groups + blockIdx.x] = s;
+    for (int i = 0; i < kBlock / kWave; ++i) c += hist[i][tid];
+    table[(size_t)t * kBins + tid] = c;
 }
 
-// vin == nullptr: the value of input element e is e + voff.
-template <typename K, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_radix_scatter(const K *__restrict__ kin,
+// Column scan of the tile-major table (rows = tiles, 256 columns = digits),
+// in three fully parallel kernels: per-chunk column sums; per digit, an
+// exclusive scan of its chunk sums (one workgroup per digit, one thread per
+// chunk) and the digit total; then every chunk rescans its rows from its
+// base, where digit d starts after the totals of all smaller digits.
+__device__ __forceinline__ void col_chunk(uint32_t rows, uint32_t chunks, uint32_t c, uint32_t *r0, uint32_t *r1) {
+    *r0 = (uint32_t)((uint64_t)rows * c / chunks);
+    *r1 = (uint32_t)((uint64_t)rows * (c + 1) / chunks);
+}
+
+__global__ __launch_bounds__(kBlock) void k_col_reduce(const uint32_t *__restrict__ table, uint32_t rows,
+                                                       uint32_t chunks, uint32_t *__restrict__ csum) {
+    uint32_t r0, r1;
+    col_chunk(rows, chunks, blockIdx.x, &r0, &r1);
+    uint32_t acc = 0;
+    for (uint32_t r = r0; r < r1; ++r) acc += table[(size_t)r * kBins + threadIdx.x];
+    csum[(size_t)blockIdx.x * kBins + threadIdx.x] = acc;
+}
+
+// Workgroup d: csum[c][d] becomes the sum over chunks < c; dtot[d] the total.
+__global__ __launch_bounds__(kBlock) void k_col_scan(uint32_t *__restrict__ csum, uint32_t chunks,
+                                                     uint32_t *__restrict__ dtot) {
+    __shared__ uint32_t s_tmp[kBlock / kWave];
+    const uint32_t d = blockIdx.x, c = threadIdx.x;
+    const uint32_t x = c < chunks ? csum[(size_t)c * kBins + d] : 0u;
+    uint32_t total;
+    const uint32_t before = dev::block_exclusive_sum(x, s_tmp, &total);
+    if (c < chunks) csum[(size_t)c * kBins + d] = before;
+    if (c == 0) dtot[d] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_col_down(uint32_t *__restrict__ table, uint32_t rows, uint32_t chunks,
+                                                     const uint32_t *__restrict__ csum,
+                                                     const uint32_t *__restrict__ dtot) {
+    __shared__ uint32_t s_tmp[kBlock / kWave];
+    uint32_t r0, r1;
+    col_chunk(rows, chunks, blockIdx.x, &r0, &r1);
+    uint32_t all;
+    const uint32_t dstart = dev::block_exclusive_sum(dtot[threadIdx.x], s_tmp, &all);
+    uint32_t run = dstart + csum[(size_t)blockIdx.x * kBins + threadIdx.x];
+    for (uint32_t r = r0; r < r1; ++r) {
+        const size_t i = (size_t)r * kBins + threadIdx.x;
+        const uint32_t x = table[i];
+        table[i] = run;
+        run += x;
+    }
+}
+
+// IMPLICIT: the value of input element e is e + voff (vin unused).
+template <typename K, int ITEMS, bool IMPLICIT>
+__global__ __launch_bounds__(kBlock, 2) void k_radix_scatter(const K *__restrict__ kin,
                                                           const uint32_t *__restrict__ vin,
                                                           K *__restrict__ kout,
                                                           uint32_t *__restrict__ vout, uint32_t n,
-                                                          uint32_t tiles, uint32_t groups, int shift,
-                                                          int nbits,
-                                                          const uint32_t *__restrict__ offs, uint32_t voff) {
+                                                          uint32_t tiles, int shift, int nbits,
+                                                          const uint32_t *__restrict__ table, uint32_t voff) {
     constexpr uint32_t TILE = kBlock * ITEMS;
     constexpr int W = kBlock / kWave;
-    __shared__ uint32_t s_cnt[W][kBins];   // per-wave digit counters, then digit bases per wave
-    __shared__ uint32_t s_base[kBins];     // global output base of every digit for this group
-    __shared__ uint32_t s_start[kBins];    // first tile-local slot of every digit
+    __shared__ uint32_t s_cnt[W][kBins];     // per-wave digit counters, then per-wave digit bases
+    __shared__ uint64_t s_match[W][kBins];   // per-wave lane masks of one item's digit
+    __shared__ uint32_t s_delta[kBins];      // global index minus tile slot, per digit
     __shared__ uint32_t s_tmp[W];
     __shared__ K s_key[TILE];
     __shared__ uint32_t s_val[TILE];
 
+    uint32_t t;
+    if (!xcd_tile(tiles, &t)) return;
     const unsigned tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
     const uint32_t mask = (1u << nbits) - 1u;
-    s_base[tid] = offs[(size_t)tid * groups + blockIdx.x];
-    uint32_t t0, t1;
-    tile_range(tiles, groups, blockIdx.x, &t0, &t1);
+    const uint32_t gbase = table[(size_t)t * kBins + tid];   // output offset of digit tid for this tile
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        s_cnt[i][tid] = 0;
+        s_match[i][tid] = 0;
+    }
+    const uint32_t base = t * TILE;
+    const uint32_t nvalid = min(TILE, n - base);
+    const uint32_t first = base + w * (kWave * ITEMS) + lane;
+    K k[ITEMS];
+    uint32_t v[ITEMS];
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t e = first + r * kWave;
+        const bool ok = e < n;
+        k[r] = ok ? kin[e] : K(0);
+        if constexpr (IMPLICIT) v[r] = e + voff;
+        else v[r] = ok ? vin[e] : 0u;
+    }
+    __syncthreads();
 
-    // The next tile's keys and values are loaded while the current tile is
-    // ranked and stored, so global-memory latency overlaps the LDS work.
-    K kn[ITEMS];
-    uint32_t vn[ITEMS];
-    auto load_tile = [&](uint32_t t) {
-        const uint32_t first = t * TILE + w * (kWave * ITEMS) + lane;
+    // Peer masks of every item: OR, read back, clear (no waits in between).
+    // dg[r] holds the item's digit, or kBins for a slot past the end.
+    uint32_t dg[ITEMS];
 #pragma unroll
-        for (int r = 0; r < ITEMS; ++r) {
-            const uint32_t e = first + r * kWave;
-            const bool ok = e < n;
-            kn[r] = ok ? kin[e] : K(0);
-            vn[r] = ok ? (vin ? vin[e] : e + voff) : 0u;
-        }
-    };
-    if (t0 < t1) load_tile(t0);
-
-    for (uint32_t t = t0; t < t1; ++t) {
-        const uint32_t base = t * TILE;
-        const uint32_t nvalid = min(TILE, n - base);
+    for (int r = 0; r < ITEMS; ++r)
+        dg[r] = (first + r * kWave < n) ? ((uint32_t)(k[r] >> shift) & mask) : (uint32_t)kBins;
+    uint32_t *mw = reinterpret_cast<uint32_t *>(&s_match[w][0]);
+    const uint32_t lbit = 1u << (lane & 31u), half = lane >> 5;
+    // Items go in chunks: the mask operations of a whole chunk are issued
+    // back to back, then its count operations, so LDS latency is paid once
+    // per chunk and few masks are live at a time.
+    constexpr int CH = (ITEMS % 8 == 0) ? 8 : 4;
+    uint32_t rk[ITEMS];
 #pragma unroll
-        for (int i = 0; i < W; ++i) s_cnt[i][tid] = 0;
-        __syncthreads();
-
-        const uint32_t wfirst = base + w * (kWave * ITEMS) + lane;
-        K k[ITEMS];
-        uint32_t v[ITEMS];
-        uint32_t rk[ITEMS];
+    for (int c0 = 0; c0 < ITEMS; c0 += CH) {
+        uint64_t pm[CH];
 #pragma unroll
-        for (int r = 0; r < ITEMS; ++r) {
-            k[r] = kn[r];
-            v[r] = vn[r];
-        }
-        if (t + 1 < t1) load_tile(t + 1);
-#pragma unroll
-        for (int r = 0; r < ITEMS; ++r) {
-            const bool ok = (wfirst + r * kWave) < n;
-            const uint32_t d = (uint32_t)(k[r] >> shift) & mask;
-            uint64_t peers = __ballot(ok);
-            for (int b = 0; b < nbits; ++b) {
-                const bool set = (d >> b) & 1u;
-                const uint64_t m = __ballot(set);
-                peers &= set ? m : ~m;
+        for (int j = 0; j < CH; ++j) {
+            const int r = c0 + j;
+            pm[j] = 0;
+            if (dg[r] < kBins) {
+                uint32_t *word = &mw[2 * dg[r]];
+                __hip_atomic_fetch_or(word + half, lbit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                pm[j] = __hip_atomic_load(reinterpret_cast<uint64_t *>(word), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_store(reinterpret_cast<uint64_t *>(word), (uint64_t)0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-            const uint32_t below = dev::count_below(peers);
+        }
+        // Ranks: the wave's running count of the digit (read before the
+        // lowest peer advances it) plus the peers below.
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int r = c0 + j;
+            const uint32_t below = dev::count_below(pm[j]);
             uint32_t old = 0;
-            if (ok) old = s_cnt[w][d];
-            // All lanes of the wave read before the lowest peer writes: LDS
-            // accesses of one wave execute in program order.
-            if (ok && below == 0) s_cnt[w][d] = old + (uint32_t)__popcll(peers);
+            if (dg[r] < kBins) {
+                uint32_t *cnt = &s_cnt[w][dg[r]];
+                old = __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (below == 0)
+                    __hip_atomic_fetch_add(cnt, (uint32_t)__popcll(pm[j]), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
             rk[r] = old + below;
         }
-        __syncthreads();
+    }
+    __syncthreads();
 
-        const uint32_t c0 = s_cnt[0][tid], c1 = s_cnt[1][tid], c2 = s_cnt[2][tid], c3 = s_cnt[3][tid];
-        const uint32_t tot = c0 + c1 + c2 + c3;
-        uint32_t all;
-        const uint32_t start = dev::block_exclusive_sum(tot, s_tmp, &all);
-        s_cnt[0][tid] = start;
-        s_cnt[1][tid] = start + c0;
-        s_cnt[2][tid] = start + c0 + c1;
-        s_cnt[3][tid] = start + c0 + c1 + c2;
-        s_start[tid] = start;
-        __syncthreads();
+    uint32_t c[W], tot = 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        c[i] = s_cnt[i][tid];
+        tot += c[i];
+    }
+    uint32_t all;
+    const uint32_t start = dev::block_exclusive_sum(tot, s_tmp, &all);
+    uint32_t run = start;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        s_cnt[i][tid] = run;
+        run += c[i];
+    }
+    s_delta[tid] = gbase - start;
+    __syncthreads();
 
 #pragma unroll
-        for (int r = 0; r < ITEMS; ++r) {
-            if ((wfirst + r * kWave) < n) {
-                const uint32_t d = (uint32_t)(k[r] >> shift) & mask;
-                const uint32_t lp = s_cnt[w][d] + rk[r];
-                s_key[lp] = k[r];
-                s_val[lp] = v[r];
-            }
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t lp = s_cnt[w][min(dg[r], (uint32_t)kBins - 1u)] + rk[r];
+        if (dg[r] < kBins && lp < TILE) {   // always true for a consistent ranking
+            s_key[lp] = k[r];
+            s_val[lp] = v[r];
         }
-        __syncthreads();
+    }
+    __syncthreads();
 
-        for (uint32_t i = tid; i < nvalid; i += kBlock) {
+    // Slot i holds the element that goes to s_delta[digit] + i.
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t i = r * kBlock + tid;
+        if (i < nvalid) {
             const K key = s_key[i];
             const uint32_t d = (uint32_t)(key >> shift) & mask;
-            const uint32_t g = s_base[d] + (i - s_start[d]);
-            kout[g] = key;
-            vout[g] = s_val[i];
+            const uint32_t g = s_delta[d] + i;
+            if (g < n) {                    // always true for a consistent count table
+                kout[g] = key;
+                vout[g] = s_val[i];
+            }
         }
-        __syncthreads();
-        s_base[tid] += tot;
     }
 }
 
@@ -258,30 +340,49 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t *__restrict__ dat
     }
 }
 
-uint32_t groups_for(uint32_t n, uint32_t tile, uint32_t *tiles) {
-    *tiles = div_up(n, tile);
-    return *tiles < kMaxGroups ? (*tiles ? *tiles : 1) : kMaxGroups;
-}
-
 template <typename K, int ITEMS>
 lor_status radix_pass_items(const K *ki, const uint32_t *vi, uint32_t voff, K *ko, uint32_t *vo, uint32_t n,
                             int shift, int nbits, uint32_t *counts, hipStream_t s) {
-    uint32_t tiles;
-    const uint32_t groups = groups_for(n, kBlock * ITEMS, &tiles);
+    constexpr uint32_t TILE = kBlock * ITEMS;
+    static_assert(TILE >= kMinTile, "tile below the size the count table is laid out for");
+    const uint32_t tiles = div_up(n, TILE);
+    const uint32_t grid = xcd_tile_grid(tiles);
     const uint32_t mask = (1u << nbits) - 1u;
-    LOR_LAUNCH("k_radix_count", (double)n * sizeof(K), s,
-               hipLaunchKernelGGL((k_radix_count<K, ITEMS>), dim3(groups), dim3(kBlock), 0, s, ki, n, tiles, groups,
-                                  shift, mask, counts));
-    LOR_TRY(scan_exclusive(counts, (uint32_t)kBins * groups, counts + (size_t)kBins * kMaxGroups, nullptr, s));
-    LOR_LAUNCH("k_radix_scatter", (double)n * ((vi ? 2.0 : 1.0) * (sizeof(K) + 4) + (vi ? 0.0 : sizeof(K))), s,
-               hipLaunchKernelGGL((k_radix_scatter<K, ITEMS>), dim3(groups), dim3(kBlock), 0, s, ki, vi, ko, vo, n,
-                                  tiles, groups, shift, nbits, counts, voff));
+    const uint32_t chunks = tiles < kColChunks ? tiles : kColChunks;
+    uint32_t *table = counts;
+    uint32_t *csum = counts + (size_t)kBins * div_up(n, kMinTile);
+    const double tbytes = 4.0 * kBins * tiles;
+    LOR_LAUNCH("k_radix_count", (double)n * sizeof(K) + tbytes, s,
+               hipLaunchKernelGGL((k_radix_count<K, ITEMS>), dim3(grid), dim3(kBlock), 0, s, ki, n, tiles, shift,
+                                  mask, table));
+    LOR_LAUNCH("k_col_reduce", tbytes, s,
+               hipLaunchKernelGGL(k_col_reduce, dim3(chunks), dim3(kBlock), 0, s, table, tiles, chunks, csum));
+    uint32_t *dtot = csum + (size_t)kBins * kColChunks;
+    LOR_LAUNCH("k_col_scan", 8.0 * kBins * chunks, s,
+               hipLaunchKernelGGL(k_col_scan, dim3(kBins), dim3(kBlock), 0, s, csum, chunks, dtot));
+    LOR_LAUNCH("k_col_down", 2.0 * tbytes, s,
+               hipLaunchKernelGGL(k_col_down, dim3(chunks), dim3(kBlock), 0, s, table, tiles, chunks, csum,
+                                  dtot));
+    const double sbytes = (double)n * ((vi ? 2.0 : 1.0) * (sizeof(K) + 4) + (vi ? 0.0 : sizeof(K))) + tbytes;
+    if (vi)
+        LOR_LAUNCH("k_radix_scatter", sbytes, s,
+                   hipLaunchKernelGGL((k_radix_scatter<K, ITEMS, false>), dim3(grid), dim3(kBlock), 0, s, ki, vi, ko,
+                                      vo, n, tiles, shift, nbits, table, voff));
+    else
+        LOR_LAUNCH("k_radix_scatter", sbytes, s,
+                   hipLaunchKernelGGL((k_radix_scatter<K, ITEMS, true>), dim3(grid), dim3(kBlock), 0, s, ki, vi, ko,
+                                      vo, n, tiles, shift, nbits, table, voff));
     return LOR_OK;
 }
 
 }  // namespace
 
-size_t radix_counts_words(uint64_t) { return (size_t)kBins * kMaxGroups + kScanTmpWords + 64; }
+// Tile-major count table sized for the smallest tile, then the chunk sums
+// and the digit totals of the column scan (workspace sizes do not depend on
+// the plan).
+size_t radix_counts_words(uint64_t n) {
+    return (size_t)kBins * (div_up(n ? n : 1, kMinTile) + kColChunks + 1) + 64;
+}
 
 lor_status scan_exclusive(uint32_t *data, uint32_t count, uint32_t *tmp, uint32_t *total, hipStream_t s) {
     if (count == 0) return LOR_OK;
@@ -321,7 +422,6 @@ lor_status radix_pass(const K *ki, const uint32_t *vi, uint32_t voff, K *ko, uin
         }
     } else {
         switch (items) {
-            case 4: return radix_pass_items<K, 4>(ki, vi, voff, ko, vo, n, shift, nbits, counts, s);
             case 12: return radix_pass_items<K, 12>(ki, vi, voff, ko, vo, n, shift, nbits, counts, s);
             case 16: return radix_pass_items<K, 16>(ki, vi, voff, ko, vo, n, shift, nbits, counts, s);
             default: return radix_pass_items<K, 8>(ki, vi, voff, ko, vo, n, shift, nbits, counts, s);

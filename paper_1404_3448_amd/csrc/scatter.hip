@@ -2,12 +2,12 @@
 //
 // A plain scatter dst[idx[i]] = val[i] with a random permutation idx puts
 // every 4-byte store on its own cache line; on MI355X such stores cost about
-// a full line of HBM traffic each. Here one stable radix pass first groups the
-// (idx, val) pairs by the top 8 bits of idx (LDS-staged, coalesced stores),
-// and a second kernel stores them in that order: the stores in flight then
-// fall into one or two 1/256 slices of dst, which stay resident in L2 and
-// the Infinity Cache, so lines are completed there before they are written
-// back.
+// a full line of HBM traffic each. Here stable radix passes first group the
+// (idx, val) pairs by the top 16 bits of idx (two 8-bit passes, LDS-staged,
+// coalesced stores), and a last kernel stores them in that order: the stores
+// an XCD has in flight then fall into one 1/65536 slice of dst (64 KB at a
+// billion entries), which stays resident in that XCD's L2 until its lines are
+// complete, so lines leave L2 whole instead of part-written.
 #include "lor_internal.hpp"
 
 namespace lor {
@@ -29,22 +29,32 @@ __global__ __launch_bounds__(kBlock) void k_scatter_local(const uint32_t *__rest
 
 }  // namespace
 
-// Digit that splits 0..dst_n-1 into at most 256 contiguous slices.
-void bucket_digit(uint32_t dst_n, int *shift, int *nbits) {
+// Digits that split 0..dst_n-1 into contiguous slices by the top (at most
+// 16) bits of an index: the high digit (top 8 bits) and the low digit (the
+// next up to 8 bits; lo_bits = 0 when dst_n needs 8 bits or fewer).
+BucketDigits bucket_digits(uint32_t dst_n) {
     const int b = dst_n > 1 ? bits_for(dst_n - 1) : 1;
-    *shift = b > 8 ? b - 8 : 0;
-    *nbits = b - *shift;
+    BucketDigits g;
+    g.hi_shift = b > 8 ? b - 8 : 0;
+    g.hi_bits = b - g.hi_shift;
+    g.lo_shift = g.hi_shift > 8 ? g.hi_shift - 8 : 0;
+    g.lo_bits = g.hi_shift - g.lo_shift;
+    return g;
 }
 
 lor_status bucketed_scatter(int32_t *dst, uint32_t dst_n, const uint32_t *idx, const uint32_t *val, uint32_t voff,
-                            uint32_t n, uint32_t *tmp_idx, uint32_t *tmp_val, uint32_t *counts, hipStream_t s) {
+                            uint32_t n, uint32_t *const tmp[4], uint32_t *counts, hipStream_t s) {
     if (n == 0) return LOR_OK;
-    int shift, nbits;
-    bucket_digit(dst_n, &shift, &nbits);
-    LOR_TRY(radix_pass<uint32_t>(idx, val, voff, tmp_idx, tmp_val, n, shift, nbits, counts, s));
+    const BucketDigits g = bucket_digits(dst_n);
+    const uint32_t *bi = tmp[0], *bv = tmp[1];
+    if (g.lo_bits > 0) {
+        LOR_TRY(radix_pass<uint32_t>(idx, val, voff, tmp[2], tmp[3], n, g.lo_shift, g.lo_bits, counts, s));
+        LOR_TRY(radix_pass<uint32_t>(tmp[2], tmp[3], 0, tmp[0], tmp[1], n, g.hi_shift, g.hi_bits, counts, s));
+    } else {
+        LOR_TRY(radix_pass<uint32_t>(idx, val, voff, tmp[0], tmp[1], n, g.hi_shift, g.hi_bits, counts, s));
+    }
     LOR_LAUNCH("k_scatter_local", 12.0 * n, s,
-               hipLaunchKernelGGL(k_scatter_local, dim3(xcd_grid(n)), dim3(kBlock), 0, s, tmp_idx, tmp_val, n, dst_n,
-                                  dst));
+               hipLaunchKernelGGL(k_scatter_local, dim3(xcd_grid(n)), dim3(kBlock), 0, s, bi, bv, n, dst_n, dst));
     return LOR_OK;
 }
 

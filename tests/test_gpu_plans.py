@@ -11,7 +11,7 @@ torch = pytest.importorskip("torch")
 
 PLANS = [
     dict(digit_bits=8, radix_items_u32=16, radix_items_u64=8, merge_items=8, plcp_steps=128),
-    dict(digit_bits=6, radix_items_u32=8, radix_items_u64=4, merge_items=4, plcp_steps=16),
+    dict(digit_bits=6, radix_items_u32=8, radix_items_u64=8, merge_items=4, plcp_steps=16),
     dict(digit_bits=7, radix_items_u32=24, radix_items_u64=16, merge_items=12, plcp_steps=512),
     dict(digit_bits=5, radix_items_u32=12, radix_items_u64=12, merge_items=8, plcp_steps=64),
 ]
