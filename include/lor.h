@@ -185,6 +185,36 @@ lor_status lor_longest_overlap_batched(const uint8_t *seqs, const int64_t *offse
                                        const void *plan, lor_overlap *out_device,
                                        void *ws, size_t ws_bytes, void *hip_stream);
 
+/* ----------------------------------- batched longest overlap, HIP graph
+ * The batched call captured once as a HIP graph and replayed. The graph is
+ * bound to seqs, offsets (copied into pinned host memory it owns), plan,
+ * out_device and ws: a replay reads the bases currently in seqs and
+ * rewrites out_device, and nothing else may use ws while the graph exists.
+ * DC3's recursion depends on the data through the name count of every
+ * level. _create runs the batch once eagerly (out_device then holds valid
+ * records), records those counts, and captures the same launch sequence
+ * with a device check per level in place of the read-back. A replay over
+ * different bases whose counts differ still stays inside its buffers, but
+ * its records are invalid: _status then returns LOR_ESTALE, and the caller
+ * runs lor_longest_overlap_batched (or creates a new graph) instead.
+ * hip_stream must not be the null stream for _create (capture needs a
+ * created stream); _launch may use any stream. Arguments and errors of
+ * _create are those of lor_longest_overlap_batched.
+ *   _launch   enqueues one replay (asynchronous)
+ *   _status   waits for hip_stream, then LOR_OK, LOR_EALPHABET (a base
+ *             outside 0..3) or LOR_ESTALE (the replay does not fit the data)
+ *   _levels   number of DC3 levels the graph holds
+ *   _destroy  frees the graph and its host memory (NULL is allowed) */
+typedef struct lor_batched_graph lor_batched_graph;
+lor_status lor_longest_overlap_batched_graph_create(const uint8_t *seqs, const int64_t *offsets,
+                                                    int32_t num_pairs, const void *plan,
+                                                    lor_overlap *out_device, void *ws, size_t ws_bytes,
+                                                    void *hip_stream, lor_batched_graph **graph);
+lor_status lor_longest_overlap_batched_graph_launch(lor_batched_graph *graph, void *hip_stream);
+lor_status lor_longest_overlap_batched_graph_status(lor_batched_graph *graph, void *hip_stream);
+int32_t lor_longest_overlap_batched_graph_levels(const lor_batched_graph *graph);
+void lor_longest_overlap_batched_graph_destroy(lor_batched_graph *graph);
+
 /* ------------------------------------------------------------ radix sort
  * Stable LSD radix sort of (key, value) pairs by key bits [bit_lo, bit_hi)
  * (Section IV: radix sort from the least to the most significant digit, the

@@ -95,7 +95,9 @@ void set_error(const char *fmt, ...) {
     va_end(ap);
 }
 
-bool timing_on() { return g_timing; }
+thread_local bool t_capturing = false;
+bool timing_on() { return g_timing && !t_capturing; }
+void set_capturing(bool on) { t_capturing = on; }
 
 bool trace_on() {
     static const bool on = getenv("LOR_TRACE") != nullptr;
@@ -404,9 +406,14 @@ size_t lor_longest_overlap_batched_workspace(int64_t total_bases, int32_t num_pa
     return batch_workspace((uint64_t)total_bases, (uint32_t)num_pairs);
 }
 
-lor_status lor_longest_overlap_batched(const uint8_t *seqs, const int64_t *offsets, int32_t num_pairs,
-                                       const void *plan, lor_overlap *out_device, void *ws, size_t ws_bytes,
-                                       void *hip_stream) {
+}  // extern "C"
+
+namespace {
+
+// Argument checks shared by the batched entry points; fills *call_plan when
+// a plan is given.
+lor_status check_batched(const uint8_t *seqs, const int64_t *offsets, int32_t num_pairs, const void *plan,
+                         const lor_overlap *out_device, void *ws, size_t ws_bytes, Plan *call_plan) {
     if (num_pairs < 1 || num_pairs > (int32_t)kMaxPairs) {
         set_error("num_pairs %d outside 1..%u", num_pairs, kMaxPairs);
         return LOR_EINVAL;
@@ -415,11 +422,10 @@ lor_status lor_longest_overlap_batched(const uint8_t *seqs, const int64_t *offse
         set_error("NULL offsets or out_device");
         return LOR_EINVAL;
     }
-    Plan call_plan{};
     if (plan) {
         const lor_plan *lp = static_cast<const lor_plan *>(plan);
-        call_plan = to_plan(lp);
-        if (lp->version != 1 || !plan_valid(call_plan)) {
+        *call_plan = to_plan(lp);
+        if (lp->version != 1 || !plan_valid(*call_plan)) {
             set_error("invalid plan");
             return LOR_EINVAL;
         }
@@ -443,13 +449,157 @@ lor_status lor_longest_overlap_batched(const uint8_t *seqs, const int64_t *offse
         set_error("seqs is NULL");
         return LOR_EINVAL;
     }
-    LOR_TRY(check_ws(ws, ws_bytes, lor_longest_overlap_batched_workspace(total, num_pairs)));
+    return check_ws(ws, ws_bytes, lor_longest_overlap_batched_workspace(total, num_pairs));
+}
+
+}  // namespace
+
+// A captured batched call: the graph, the pinned host tables its copy nodes
+// read, and the workspace header its device checks write.
+struct lor_batched_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t *h_start = nullptr;
+    int32_t *h_alen = nullptr;
+    int64_t *h_src = nullptr;
+    uint32_t *hdr = nullptr;
+    uint32_t levels = 0;
+};
+
+namespace {
+void free_graph(lor_batched_graph *g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->h_start) (void)hipHostFree(g->h_start);
+    if (g->h_alen) (void)hipHostFree(g->h_alen);
+    if (g->h_src) (void)hipHostFree(g->h_src);
+    delete g;
+}
+}  // namespace
+
+extern "C" {
+
+lor_status lor_longest_overlap_batched(const uint8_t *seqs, const int64_t *offsets, int32_t num_pairs,
+                                       const void *plan, lor_overlap *out_device, void *ws, size_t ws_bytes,
+                                       void *hip_stream) {
+    Plan call_plan{};
+    LOR_TRY(check_batched(seqs, offsets, num_pairs, plan, out_device, ws, ws_bytes, &call_plan));
     if (plan) plan_set_thread(&call_plan);
     const lor_status st =
         batch_overlap(seqs, offsets, (uint32_t)num_pairs, out_device, ws, ws_bytes, (hipStream_t)hip_stream);
     plan_set_thread(nullptr);
     return st;
 }
+
+lor_status lor_longest_overlap_batched_graph_create(const uint8_t *seqs, const int64_t *offsets, int32_t num_pairs,
+                                                    const void *plan, lor_overlap *out_device, void *ws,
+                                                    size_t ws_bytes, void *hip_stream, lor_batched_graph **graph) {
+    if (!graph) {
+        set_error("NULL graph");
+        return LOR_EINVAL;
+    }
+    *graph = nullptr;
+    if (!hip_stream) {
+        set_error("graph capture needs a stream other than the null stream");
+        return LOR_EINVAL;
+    }
+    Plan call_plan{};
+    LOR_TRY(check_batched(seqs, offsets, num_pairs, plan, out_device, ws, ws_bytes, &call_plan));
+    const uint32_t P = (uint32_t)num_pairs;
+    hipStream_t s = (hipStream_t)hip_stream;
+    lor_batched_graph *g = new lor_batched_graph;
+    g->hdr = static_cast<uint32_t *>(ws);
+    lor_status st = LOR_OK;
+    if (hipHostMalloc((void **)&g->h_start, ((size_t)P + 1) * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&g->h_alen, (size_t)P * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&g->h_src, 2ull * P * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+        set_error("pinned host allocation failed");
+        free_graph(g);
+        return LOR_EHIP;
+    }
+    const uint64_t N = batch_tables(offsets, P, g->h_start, g->h_alen, g->h_src);
+    if (plan) plan_set_thread(&call_plan);
+    DecisionTape tape;
+    set_decision_tape(&tape);
+    // 1. eager run: results, and the name count of every DC3 level
+    st = batch_overlap_run(seqs, P, N, g->h_start, g->h_alen, g->h_src, out_device, ws, ws_bytes, s);
+    if (st == LOR_OK && hipStreamSynchronize(s) != hipSuccess) {
+        set_error("hipStreamSynchronize failed");
+        st = LOR_EHIP;
+    }
+    // 2. the same launch sequence under capture, checks in place of read-backs
+    if (st == LOR_OK) {
+        tape.replay = true;
+        tape.next = 0;
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            set_error("hipStreamBeginCapture failed");
+            st = LOR_EHIP;
+        } else {
+            set_capturing(true);
+            st = batch_overlap_run(seqs, P, N, g->h_start, g->h_alen, g->h_src, out_device, ws, ws_bytes, s);
+            set_capturing(false);
+            hipGraph_t graph_obj = nullptr;
+            const hipError_t e = hipStreamEndCapture(s, &graph_obj);
+            g->graph = graph_obj;
+            if (st == LOR_OK && (e != hipSuccess || !graph_obj)) {
+                set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e));
+                st = LOR_EHIP;
+            }
+            if (st == LOR_OK && tape.next != tape.names.size()) {
+                set_error("internal: captured %zu of %zu DC3 levels", tape.next, tape.names.size());
+                st = LOR_EINVAL;
+            }
+            if (st == LOR_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+                set_error("hipGraphInstantiate failed");
+                st = LOR_EHIP;
+            }
+        }
+    }
+    g->levels = (uint32_t)tape.names.size();
+    set_decision_tape(nullptr);
+    plan_set_thread(nullptr);
+    if (st != LOR_OK) {
+        free_graph(g);
+        return st;
+    }
+    *graph = g;
+    return LOR_OK;
+}
+
+lor_status lor_longest_overlap_batched_graph_launch(lor_batched_graph *graph, void *hip_stream) {
+    if (!graph || !graph->exec) {
+        set_error("NULL graph");
+        return LOR_EINVAL;
+    }
+    LOR_HIP(hipGraphLaunch(graph->exec, (hipStream_t)hip_stream));
+    return LOR_OK;
+}
+
+lor_status lor_longest_overlap_batched_graph_status(lor_batched_graph *graph, void *hip_stream) {
+    if (!graph) {
+        set_error("NULL graph");
+        return LOR_EINVAL;
+    }
+    uint32_t words[16];
+    LOR_HIP(hipMemcpyAsync(words, graph->hdr, sizeof(words), hipMemcpyDeviceToHost, (hipStream_t)hip_stream));
+    LOR_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
+    if (words[0]) {
+        set_error("input base outside 0..3");
+        return LOR_EALPHABET;
+    }
+    if (words[kStaleWord]) {
+        set_error("the data changed the DC3 name counts the graph was captured with; results are invalid");
+        return LOR_ESTALE;
+    }
+    return LOR_OK;
+}
+
+int32_t lor_longest_overlap_batched_graph_levels(const lor_batched_graph *graph) {
+    return graph ? (int32_t)graph->levels : -1;
+}
+
+void lor_longest_overlap_batched_graph_destroy(lor_batched_graph *graph) { free_graph(graph); }
 
 size_t lor_sort_pairs_workspace(int64_t n, int32_t key_bytes) {
     if (n < 0 || n > INT32_MAX || (key_bytes != 4 && key_bytes != 8)) return 0;

@@ -323,11 +323,8 @@ size_t batch_workspace(uint64_t total_bases, uint32_t P) {
     return fixed + phase + 4096;
 }
 
-lor_status batch_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t P, lor_overlap *out, void *ws,
-                         size_t ws_bytes, hipStream_t s) {
+uint64_t batch_tables(const int64_t *offsets, uint32_t P, int32_t *h_start, int32_t *h_alen, int64_t *h_src) {
     uint64_t N = 0;
-    std::vector<int32_t> h_start(P + 1), h_alen(P);
-    std::vector<int64_t> h_src(2 * (size_t)P);
     for (uint32_t p = 0; p < P; ++p) {
         const int64_t a = offsets[2 * p + 1] - offsets[2 * p], b = offsets[2 * p + 2] - offsets[2 * p + 1];
         h_start[p] = (int32_t)N;
@@ -337,7 +334,12 @@ lor_status batch_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t P
         N += (uint64_t)(a + b + 2);
     }
     h_start[P] = (int32_t)N;
+    return N;
+}
 
+lor_status batch_overlap_run(const uint8_t *seqs, uint32_t P, uint64_t N, const int32_t *h_start,
+                             const int32_t *h_alen, const int64_t *h_src, lor_overlap *out, void *ws,
+                             size_t ws_bytes, hipStream_t s) {
     Arena ar;
     ar.base = static_cast<char *>(ws);
     ar.cap = ws_bytes;
@@ -358,14 +360,13 @@ lor_status batch_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t P
     LOR_TAKE(ar, unsigned long long, P, best);
     const size_t phase = ar.mark();
 
-    LOR_HIP(hipMemcpyAsync(start, h_start.data(), (P + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    LOR_HIP(hipMemcpyAsync(alen, h_alen.data(), P * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    LOR_HIP(hipMemcpyAsync(src, h_src.data(), 2ull * P * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    LOR_HIP(hipMemcpyAsync(start, h_start, (P + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LOR_HIP(hipMemcpyAsync(alen, h_alen, P * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LOR_HIP(hipMemcpyAsync(src, h_src, 2ull * P * sizeof(int64_t), hipMemcpyHostToDevice, s));
     LOR_TRY(zero_words(hdr, 16, s));
     LOR_LAUNCH("k_join_pairs", 3.0 * N, s,
                hipLaunchKernelGGL(k_join_pairs, dim3(grid_for(N)), dim3(kBlock), 0, s, seqs, start, alen, src, P,
                                   (uint32_t)N, text, hdr));
-    // DC3 reads back one word per level, which also orders the host copies above
     LOR_TRY(dc3_u16(text, (uint32_t)N, 8u * (P - 1) + 6u, sa, ar, hdr, s));
     ar.release(phase);
     LOR_TRY(lcp_build_u16(text, (uint32_t)N, sa, lcp, nullptr, ar, s));
@@ -387,7 +388,17 @@ lor_status batch_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t P
     LOR_LAUNCH("k_pair_records", 32.0 * P, s,
                hipLaunchKernelGGL(k_pair_records, dim3(grid_for(P)), dim3(kBlock), 0, s, start, alen, P, lmax, best,
                                   out));
-    LOR_HIP(hipStreamSynchronize(s));   // host tables above must outlive their copies
+    return LOR_OK;
+}
+
+lor_status batch_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t P, lor_overlap *out, void *ws,
+                         size_t ws_bytes, hipStream_t s) {
+    std::vector<int32_t> h_start(P + 1), h_alen(P);
+    std::vector<int64_t> h_src(2 * (size_t)P);
+    const uint64_t N = batch_tables(offsets, P, h_start.data(), h_alen.data(), h_src.data());
+    // DC3 reads back one word per level, which also orders the host copies
+    LOR_TRY(batch_overlap_run(seqs, P, N, h_start.data(), h_alen.data(), h_src.data(), out, ws, ws_bytes, s));
+    LOR_HIP(hipStreamSynchronize(s));   // the host tables must outlive their copies
     return LOR_OK;
 }
 

@@ -528,6 +528,14 @@ struct HostHdr {
     uint32_t maxname;
 };
 
+// Replayed launch sequences: flag the header when this level's name count
+// differs from the recorded one (lane 0 stores; vector memory only).
+__global__ __launch_bounds__(kWave) void k_expect_names(uint32_t *hdr, uint32_t expected) {
+    if (threadIdx.x == 0 && hdr[1] != expected) hdr[kStaleWord] = 1u;
+}
+
+thread_local DecisionTape *t_tape = nullptr;
+
 enum KeyMode { KM_U32, KM_U64, KM_STAGED };
 
 template <typename CH>
@@ -686,8 +694,21 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     bool unique = true;
     if (run) {
         HostHdr h;
-        LOR_HIP(hipMemcpyAsync(&h, hdr, sizeof(h), hipMemcpyDeviceToHost, s));
-        LOR_HIP(hipStreamSynchronize(s));
+        DecisionTape *tape = decision_tape();
+        if (tape && tape->replay) {
+            if (tape->next >= tape->names.size()) {
+                set_error("internal: launch sequence longer than the recorded one");
+                return LOR_EINVAL;
+            }
+            h.error = 0;
+            h.maxname = tape->names[tape->next++];
+            LOR_LAUNCH("k_expect_names", 8.0, s,
+                       hipLaunchKernelGGL(k_expect_names, dim3(1), dim3(kWave), 0, s, hdr, h.maxname));
+        } else {
+            LOR_HIP(hipMemcpyAsync(&h, hdr, sizeof(h), hipMemcpyDeviceToHost, s));
+            LOR_HIP(hipStreamSynchronize(s));
+            if (tape) tape->names.push_back(h.maxname);
+        }
         if (h.error) {
             set_error("input base outside 0..3");
             return LOR_EALPHABET;
@@ -799,6 +820,9 @@ lor_status dc3_u16(const uint16_t *text, uint32_t n, uint32_t alphabet, int32_t 
                    hipStream_t s) {
     return dc3_level<uint16_t>(text, n, alphabet, sa, ar, hdr, s, 0);
 }
+
+void set_decision_tape(DecisionTape *tape) { t_tape = tape; }
+DecisionTape *decision_tape() { return t_tape; }
 
 size_t dc3_workspace_bound(uint64_t n) {
     Arena ar;   // measuring

@@ -7,6 +7,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "lor.h"
 
 namespace lor {
@@ -78,6 +80,24 @@ struct WsHeader {
     uint32_t word[15];
 };
 constexpr size_t kHeaderBytes = 256;
+constexpr int kStaleWord = 15;   // header word set when a replayed launch sequence no longer fits the data
+
+// ------------------------------------------------ captured launch sequences
+// The only data-dependent host decision of DC3 is the name count of every
+// level (it decides recursion and the key width of the next level). An eager
+// run records the counts; a run under stream capture replays them and, in
+// place of each read-back, launches a device check that sets header word
+// kStaleWord when the data give a different count. Every kernel bounds its
+// memory accesses by sizes the host passes, so a replay whose check fails
+// still stays inside its buffers; its results are then discarded.
+struct DecisionTape {
+    std::vector<uint32_t> names;   // name count per DC3 level, in call order
+    size_t next = 0;
+    bool replay = false;           // under capture: take recorded counts, emit checks
+};
+void set_decision_tape(DecisionTape *tape);   // for the calling thread; nullptr turns it off
+DecisionTape *decision_tape();
+void set_capturing(bool on);                  // no event timing while a stream is captured
 
 // Device count of compute units (queried once per device).
 int num_cus();
@@ -231,6 +251,13 @@ constexpr uint32_t kMaxPairs = 8191;   // tags 0..8190: 8 * tag + 6 fits 16 bits
 size_t batch_workspace(uint64_t total_bases, uint32_t num_pairs);
 lor_status batch_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t num_pairs, lor_overlap *out,
                          void *ws, size_t ws_bytes, hipStream_t s);
+// The two halves of batch_overlap, for launch-sequence capture: host tables
+// of the pairs (returns the tagged length N), and the device work without
+// any final synchronisation (the host tables must outlive the copies).
+uint64_t batch_tables(const int64_t *offsets, uint32_t num_pairs, int32_t *h_start, int32_t *h_alen, int64_t *h_src);
+lor_status batch_overlap_run(const uint8_t *seqs, uint32_t num_pairs, uint64_t N, const int32_t *h_start,
+                             const int32_t *h_alen, const int64_t *h_src, lor_overlap *out, void *ws,
+                             size_t ws_bytes, hipStream_t s);
 lor_status overlap_scan(const int32_t *sa, const int32_t *lcp, uint32_t n, const SeqStarts &st,
                         Arena &ar, hipStream_t s, int64_t result[5]);
 

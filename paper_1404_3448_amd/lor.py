@@ -93,6 +93,11 @@ def lib():
         "lor_longest_overlap": ([P, P, I64, P, I32, ctypes.POINTER(lor_overlap), P, SZ, P], I32),
         "lor_longest_overlap_batched_workspace": ([I64, I32], SZ),
         "lor_longest_overlap_batched": ([P, P, I32, P, P, P, SZ, P], I32),
+        "lor_longest_overlap_batched_graph_create": ([P, P, I32, P, P, P, SZ, P, ctypes.POINTER(P)], I32),
+        "lor_longest_overlap_batched_graph_launch": ([P, P], I32),
+        "lor_longest_overlap_batched_graph_status": ([P, P], I32),
+        "lor_longest_overlap_batched_graph_levels": ([P], I32),
+        "lor_longest_overlap_batched_graph_destroy": ([P], None),
         "lor_sort_pairs_workspace": ([I64, I32], SZ),
         "lor_sort_pairs_u32": ([P, P, I64, I32, I32, P, SZ, P], I32),
         "lor_sort_pairs_u64": ([P, P, I64, I32, I32, P, SZ, P], I32),
@@ -330,6 +335,67 @@ def lor_longest_overlap_batched(seqs, offsets, out=None, ws=None, stream=None, p
                                            _ptr(ws), ws.numel() * ws.element_size(), _stream(stream))
     _check("lor_longest_overlap_batched", st)
     return out
+
+
+class BatchedGraph:
+    """A batched call captured as a HIP graph (lor_longest_overlap_batched_graph_*).
+    Holds the tensors it is bound to; launch() enqueues a replay, status()
+    waits and raises LorError (LOR_ESTALE) when the replay no longer fits the
+    data in `seqs`."""
+
+    def __init__(self, handle, seqs, out, ws, offsets):
+        self._h = handle
+        self.seqs, self.out, self.ws, self.offsets = seqs, out, ws, offsets
+
+    @property
+    def levels(self) -> int:
+        return int(lib().lor_longest_overlap_batched_graph_levels(self._h))
+
+    def launch(self, stream=None):
+        _check("lor_longest_overlap_batched_graph_launch",
+               lib().lor_longest_overlap_batched_graph_launch(self._h, _stream(stream)))
+        return self.out
+
+    def status(self, stream=None) -> int:
+        st = lib().lor_longest_overlap_batched_graph_status(self._h, _stream(stream))
+        _check("lor_longest_overlap_batched_graph_status", st)
+        return st
+
+    def close(self):
+        if self._h:
+            lib().lor_longest_overlap_batched_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lor_longest_overlap_batched_graph_create(seqs, offsets, stream, out=None, ws=None, plan=None) -> BatchedGraph:
+    """Capture lor_longest_overlap_batched for these buffers as a HIP graph
+    (stream: a created torch stream, not the null stream). `out` holds valid
+    records on return."""
+    import torch
+    o = _offsets(offsets)
+    if (o.size - 1) % 2:
+        raise ValueError("offsets: need int64[2 * num_pairs + 1]")
+    P = (o.size - 1) // 2
+    _need(seqs, torch.uint8, int(o[-1]), "seqs")
+    if out is None:
+        out = torch.empty(P * ctypes.sizeof(lor_overlap), dtype=torch.uint8, device=seqs.device)
+    nbytes = lor_longest_overlap_batched_workspace(int(o[-1]), P)
+    ws = _workspace(nbytes, seqs.device, ws)
+    pl = None
+    if plan is not None:
+        pl = ctypes.byref(plan if isinstance(plan, lor_plan) else make_plan(**plan))
+    h = ctypes.c_void_p()
+    st = lib().lor_longest_overlap_batched_graph_create(_ptr(seqs), o.ctypes.data_as(ctypes.c_void_p), P, pl,
+                                                        _ptr(out), _ptr(ws), ws.numel() * ws.element_size(),
+                                                        _stream(stream), ctypes.byref(h))
+    _check("lor_longest_overlap_batched_graph_create", st)
+    return BatchedGraph(h, seqs, out, ws, o)
 
 
 def records_to_tuples(out) -> list:

@@ -110,3 +110,23 @@ def test_plan_validation():
     lor.lor_plan_set({"merge_items": 4, "digit_bits": 4})
     assert lor.lor_build_sa_workspace(1 << 20, 2) == a
     lor.lor_plan_set(None)
+
+
+def test_graph_argument_errors(L):
+    o, op = offsets(0, 5, 9)
+    h = ctypes.c_void_p()
+    ws = lor.lor_longest_overlap_batched_workspace(9, 1)
+    # the null stream cannot be captured
+    assert L.lor_longest_overlap_batched_graph_create(FAKE, op, 1, None, FAKE, FAKE, ws, None,
+                                                      ctypes.byref(h)) == lor.LOR_EINVAL
+    assert b"null stream" in L.lor_last_error()
+    assert L.lor_longest_overlap_batched_graph_create(FAKE, op, 1, None, FAKE, FAKE, ws, FAKE, None) == lor.LOR_EINVAL
+    assert L.lor_longest_overlap_batched_graph_create(FAKE, op, 0, None, FAKE, FAKE, ws, FAKE,
+                                                      ctypes.byref(h)) == lor.LOR_EINVAL
+    assert L.lor_longest_overlap_batched_graph_create(FAKE, op, 1, None, FAKE, FAKE, ws - 1, FAKE,
+                                                      ctypes.byref(h)) == lor.LOR_EWORKSPACE
+    assert not h.value
+    assert L.lor_longest_overlap_batched_graph_launch(None, None) == lor.LOR_EINVAL
+    assert L.lor_longest_overlap_batched_graph_status(None, None) == lor.LOR_EINVAL
+    assert L.lor_longest_overlap_batched_graph_levels(None) == -1
+    L.lor_longest_overlap_batched_graph_destroy(None)
