@@ -11,7 +11,7 @@ JSON keyed by the GPU architecture:
 
 A plan changes speed only; results are identical under every plan.
 
-    python -m paper_1404_3448_amd.autotune            # writes plans/<arch>.json
+    python -m paper_1404_3448_amd.autotune [--out DIR]   # writes plans/<arch>.json (or DIR/<arch>.json)
 """
 from __future__ import annotations
 
@@ -139,9 +139,13 @@ def tune(log=print) -> dict:
 
 
 def main():
+    import argparse
+    ap = argparse.ArgumentParser(description="tune the kernel plan of liblor.so on this GPU")
+    ap.add_argument("--out", default=PLAN_DIR, help="directory for <arch>.json (default: the package's plans/)")
+    args = ap.parse_args()
     doc = tune(log=lambda *a: print(*a, file=sys.stderr, flush=True))
-    os.makedirs(PLAN_DIR, exist_ok=True)
-    path = plan_path(doc["arch"])
+    os.makedirs(args.out, exist_ok=True)
+    path = os.path.join(args.out, f"{doc['arch']}.json")
     with open(path, "w") as f:
         json.dump(doc, f, indent=1)
     print(json.dumps(doc["plan"]))
