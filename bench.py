@@ -84,10 +84,27 @@ def cpu_baseline(seqs, seq_cut: int, nseq: int, threads: int) -> dict:
     lcp = oracle.lcp(joined, sa, nthreads=threads)
     oracle.overlap(sa, lcp, offs)
     dt = time.perf_counter() - t0
+    # one core, on a smaller sample of the same text
+    sub1 = [s[: 1 << 22] for s in seqs[:2]]
+    offs1 = np.concatenate([[0], np.cumsum([s.size for s in sub1])]).astype(np.int64)
+    t1 = time.perf_counter()
+    j1 = oracle.join(np.concatenate(sub1), offs1)
+    sa1 = oracle.suffix_array(j1, nthreads=1)
+    oracle.overlap(sa1, oracle.lcp(j1, sa1, nthreads=1), offs1)
+    dt1 = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(joined.size / dt / 1e6, 3), "unit": "Msuffixes/s", "cores": threads, "kind": "oracle",
             "sample": f"first {nseq} sequences cut to {seq_cut} bases (N = {joined.size}); join + "
                       f"comparison-sort SA + direct LCP + overlap scan, {dt:.2f} s",
-            "seconds": round(dt, 3)}
+            "seconds": round(dt, 3),
+            "single_core": {"value": round(j1.size / dt1 / 1e6, 3), "unit": "Msuffixes/s",
+                            "sample": f"first 2 sequences cut to {1 << 22} bases (N = {j1.size}), {dt1:.2f} s"},
+            "cpu_model": model, "nproc": os.cpu_count()}
 
 
 def bench_batched(lor, synth, torch, reps: int = 3) -> dict:
@@ -350,6 +367,10 @@ def main():
         "batched": batched,
         "serving": serving,
         "cpu_baseline": cpu,
+        "paper_context": {"claim": "more than 20x over a serial CPU run (abstract, Section I)",
+                          "hardware": "Intel Core i3-3110M host, GeForce 610M",
+                          "gpu_over_single_core_oracle": (round(value / cpu["single_core"]["value"], 1)
+                                                          if cpu else None)},
     }
     print(json.dumps(out), flush=True)
 

@@ -36,7 +36,7 @@ namespace {
 constexpr int kDigitBits = 8;
 constexpr int kBins = 1 << kDigitBits;
 constexpr uint32_t kMinTile = kBlock * 8;   // smallest tile of any plan (sizes the count table)
-constexpr uint32_t kColChunks = 256;        // row chunks of the column scan
+constexpr uint32_t kColChunks = 1024;       // row chunks of the column scan (4 per scan thread)
 
 // Tile handled by this workgroup: XCD x = blockIdx mod 8 takes the x-th
 // eighth of the tiles, in workgroup order. Returns false for the padding
@@ -100,15 +100,26 @@ __global__ __launch_bounds__(kBlock) void k_col_reduce(const uint32_t *__restric
 }
 
 // Workgroup d: csum[c][d] becomes the sum over chunks < c; dtot[d] the total.
+// Thread j owns chunks 4j .. 4j+3.
+constexpr uint32_t kColPer = kColChunks / kBlock;
 __global__ __launch_bounds__(kBlock) void k_col_scan(uint32_t *__restrict__ csum, uint32_t chunks,
                                                      uint32_t *__restrict__ dtot) {
     __shared__ uint32_t s_tmp[kBlock / kWave];
-    const uint32_t d = blockIdx.x, c = threadIdx.x;
-    const uint32_t x = c < chunks ? csum[(size_t)c * kBins + d] : 0u;
+    const uint32_t d = blockIdx.x, c0 = threadIdx.x * kColPer;
+    uint32_t x[kColPer], sum = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kColPer; ++q) {
+        x[q] = c0 + q < chunks ? csum[(size_t)(c0 + q) * kBins + d] : 0u;
+        sum += x[q];
+    }
     uint32_t total;
-    const uint32_t before = dev::block_exclusive_sum(x, s_tmp, &total);
-    if (c < chunks) csum[(size_t)c * kBins + d] = before;
-    if (c == 0) dtot[d] = total;
+    uint32_t run = dev::block_exclusive_sum(sum, s_tmp, &total);
+#pragma unroll
+    for (uint32_t q = 0; q < kColPer; ++q) {
+        if (c0 + q < chunks) csum[(size_t)(c0 + q) * kBins + d] = run;
+        run += x[q];
+    }
+    if (threadIdx.x == 0) dtot[d] = total;
 }
 
 __global__ __launch_bounds__(kBlock) void k_col_down(uint32_t *__restrict__ table, uint32_t rows, uint32_t chunks,

@@ -9,7 +9,8 @@
 // tile of level k0-1 plus the halo the next five levels reach into, and
 // computes and writes those levels from LDS, so level k0-1 is read once for
 // five levels. Higher levels (windows wider than a tile) are built one at a
-// time from level k-1 (two streaming reads, one write per entry). With 288 GB of HBM the table fits next to
+// time from level k-1 (two streaming reads, one write per entry; tiles are
+// ordered so that most entries are fetched from HBM once). With 288 GB of HBM the table fits next to
 // the 1G-suffix arrays, and every query costs four independent gathers
 // (two ISA entries, two table entries) instead of a pointer walk.
 #include <climits>
@@ -20,10 +21,40 @@ namespace lor {
 
 namespace {
 
+// One level from the previous one, a tile of kLvTile outputs per workgroup.
+// Entry x of the previous level is read twice: by output tile x's workgroup
+// and by the one 2^(k-1) entries to its left. When that distance spans H >= 1
+// tiles, tiles t and t + H are taken one right after the other (order within
+// groups of 2H tiles: 0, H, 1, H + 1, ...), so the second read of the shared
+// tile finds it in L2; the sequence is dealt to the XCDs in contiguous
+// eighths so that partners run on the same XCD.
+constexpr uint32_t kLvItems = 16;
+constexpr uint32_t kLvTile = kBlock * kLvItems;
+
 __global__ __launch_bounds__(kBlock) void k_st_level(const int32_t *__restrict__ prev, uint32_t half,
-                                                     uint32_t cnt, int32_t *__restrict__ cur) {
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock)
-        cur[i] = min(prev[i], prev[i + half]);
+                                                     uint32_t cnt, uint32_t tiles, int32_t *__restrict__ cur) {
+    const uint32_t per = (tiles + kXcds - 1) / kXcds;
+    const uint32_t j = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;   // place in the sequence
+    if (blockIdx.x / kXcds >= per || j >= tiles) return;
+    const uint32_t H = half / kLvTile;
+    uint32_t t = j;
+    if (H >= 1) {
+        const uint32_t G = 2 * H, g = j / G, k = j % G;
+        if ((uint64_t)(g + 1) * G <= tiles) t = g * G + (k >> 1) + (k & 1u) * H;   // a partial last group keeps plain order
+    }
+    const uint32_t i0 = t * kLvTile + threadIdx.x;
+    int32_t a[kLvItems], b[kLvItems];
+#pragma unroll
+    for (int r = 0; r < (int)kLvItems; ++r) {
+        const uint32_t i = i0 + r * kBlock;
+        a[r] = i < cnt ? prev[i] : 0;
+        b[r] = i < cnt ? prev[i + half] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < (int)kLvItems; ++r) {
+        const uint32_t i = i0 + r * kBlock;
+        if (i < cnt) cur[i] = min(a[r], b[r]);
+    }
 }
 
 constexpr uint32_t kStTile = kBlock * 16;   // outputs per workgroup in fused levels
@@ -152,8 +183,10 @@ lor_status rmq_build_levels(const int32_t *lcp, uint32_t n, int32_t *table, int 
         int32_t *cur = table + rmq_level_offset(n, k);
         const uint32_t half = 1u << (k - 1);
         const uint32_t cnt = n - (1u << k) + 1u;
+        const uint32_t tiles = div_up(cnt, kLvTile);
         LOR_LAUNCH("k_st_level", (double)cnt * 8, s,
-                   hipLaunchKernelGGL(k_st_level, dim3(grid_for(cnt)), dim3(kBlock), 0, s, prev, half, cnt, cur));
+                   hipLaunchKernelGGL(k_st_level, dim3(kXcds * div_up(tiles, kXcds)), dim3(kBlock), 0, s, prev, half,
+                                      cnt, tiles, cur));
     }
     return LOR_OK;
 }

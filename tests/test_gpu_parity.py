@@ -46,7 +46,7 @@ def _keys_u32(rng, n, mode):
     return rng.integers(0, 300, size=n).astype(np.uint32) << np.uint32(rng.integers(0, 20))
 
 
-@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 1000, 4095, 4096, 4097, 262147, 1 << 20])
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 1000, 4095, 4096, 4097, 262147, 1 << 20, (1 << 22) + 12345])
 @pytest.mark.parametrize("bits", [(0, 32), (0, 8), (3, 17), (0, 15)])
 @pytest.mark.parametrize("mode", ["wide", "dups", "skew"])
 def test_sort_pairs_u32(n, bits, mode):
@@ -64,7 +64,7 @@ def test_sort_pairs_u32(n, bits, mode):
     assert np.array_equal(host(v), vals[order])
 
 
-@pytest.mark.parametrize("n", [1, 100, 3073, 200001])
+@pytest.mark.parametrize("n", [1, 100, 3073, 200001, (1 << 21) + 77])
 @pytest.mark.parametrize("bits", [(0, 64), (5, 45), (0, 21)])
 def test_sort_pairs_u64(n, bits):
     say("sort u64", n, bits)
