@@ -401,9 +401,24 @@ __global__ __launch_bounds__(kBlock) void k_ns_count(const int32_t *__restrict__
     if (threadIdx.x == 0) counts[blockIdx.x] = tot;
 }
 
-// Emit mod-0 position 3*idx (predecessor of mod-1 entry idx) with key t_{3 idx}.
+// The first symbol of every mod-0 suffix, laid out by the rank of the
+// mod-1 suffix that follows it: for R-index q < n0 (position 3q+1), the pair
+// (rank(3q+1) - 1, t_{3q}). A bucketed scatter of these pairs puts t_{3q}
+// at sample-order slot rank(3q+1) - 1, so Step 2 then reads its keys in
+// order instead of gathering one text symbol per mod-0 suffix.
 template <typename CH>
-__global__ __launch_bounds__(kBlock) void k_ns_write(const CH *__restrict__ t, const int32_t *__restrict__ sa12,
+__global__ __launch_bounds__(kBlock) void k_ns_pairs(const CH *__restrict__ t, Dims d,
+                                                     const int32_t *__restrict__ rank12,
+                                                     uint32_t *__restrict__ slot, uint32_t *__restrict__ sym0) {
+    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < d.n0; q += gridDim.x * kBlock) {
+        slot[q] = (uint32_t)rank12[q] - 1u;
+        sym0[q] = sym(t, d.n, 3u * q);
+    }
+}
+
+// Emit mod-0 position 3*idx (predecessor of mod-1 entry idx) with key
+// t_{3 idx}, which first[r] holds for sample-order slot r.
+__global__ __launch_bounds__(kBlock) void k_ns_write(const int32_t *__restrict__ first, const int32_t *__restrict__ sa12,
                                                      Dims d, uint32_t groups,
                                                      const uint32_t *__restrict__ counts,
                                                      uint32_t *__restrict__ keys0,
@@ -427,10 +442,9 @@ __global__ __launch_bounds__(kBlock) void k_ns_write(const CH *__restrict__ t, c
 #pragma unroll
         for (int i = 0; i < kScanItems; ++i) {
             if (idx[i] < d.n0) {
-                const uint32_t p = 3u * idx[i];
                 if (j < d.n0) {
-                    keys0[j] = sym(t, d.n, p);
-                    vals0[j] = p;
+                    keys0[j] = (uint32_t)first[r0 + i];
+                    vals0[j] = 3u * idx[i];
                 }
                 ++j;
             }
@@ -753,11 +767,13 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
                                       rec));
 
     // ---- Step 2: mod-0 suffixes
-    uint32_t *keys0, *vals0, *keys1, *vals1, *counts2;
+    uint32_t *keys0, *vals0, *keys1, *vals1, *sc0, *sc1, *counts2;
     LOR_TAKE(ar, uint32_t, d.n0, keys0);
     LOR_TAKE(ar, uint32_t, d.n0, vals0);
     LOR_TAKE(ar, uint32_t, d.n0, keys1);
     LOR_TAKE(ar, uint32_t, d.n0, vals1);
+    LOR_TAKE(ar, uint32_t, d.n0, sc0);
+    LOR_TAKE(ar, uint32_t, d.n0, sc1);
     LOR_TAKE(ar, uint32_t, radix_counts_words(d.n0) + kMaxScanGroups + 64, counts2);
     uint32_t *gcount2 = counts2 + radix_counts_words(d.n0);
     const int mitems = plan().merge_items;
@@ -766,12 +782,19 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     uint32_t *split;   // sized for the smallest merge tile, so the workspace does not depend on the plan
     LOR_TAKE(ar, uint32_t, (size_t)div_up(n, kBlock * 4) + 2, split);
     if (run) {
+        // first symbols of the mod-0 suffixes in sample order, into R (the
+        // ranks are consumed by k_ns_pairs; the records already hold them)
+        LOR_LAUNCH("k_ns_pairs", (double)d.n0 * (12 + sizeof(CH)), s,
+                   hipLaunchKernelGGL(k_ns_pairs<CH>, dim3(grid_for(d.n0)), dim3(kBlock), 0, s, t, d, rank12, keys0,
+                                      vals0));
+        uint32_t *const tmp4[4] = {keys1, vals1, sc0, sc1};
+        LOR_TRY(bucketed_scatter(R, d.m, keys0, vals0, 0, d.n0, tmp4, counts2, s));
         const uint32_t G = scan_groups(d.m);
         LOR_LAUNCH("k_ns_count", (double)d.m * 4, s,
                    hipLaunchKernelGGL(k_ns_count, dim3(G), dim3(kBlock), 0, s, sa12, d, G, gcount2));
         LOR_TRY(scan_block_totals(gcount2, G, hdr + 2, s));
-        LOR_LAUNCH("k_ns_write", (double)d.m * 4 + (double)d.n0 * (8 + sizeof(CH)), s,
-                   hipLaunchKernelGGL(k_ns_write<CH>, dim3(G), dim3(kBlock), 0, s, t, sa12, d, G, gcount2, keys0,
+        LOR_LAUNCH("k_ns_write", (double)d.m * 4 + (double)d.n0 * 12, s,
+                   hipLaunchKernelGGL(k_ns_write, dim3(G), dim3(kBlock), 0, s, R, sa12, d, G, gcount2, keys0,
                                       vals0));
         bool alt;
         LOR_TRY(radix_sort<uint32_t>(keys0, vals0, keys1, vals1, d.n0, 0, b, counts2, s, &alt));

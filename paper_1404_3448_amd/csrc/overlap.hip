@@ -109,24 +109,39 @@ __global__ __launch_bounds__(kBlock) void k_init(uint32_t *w, int count) {
     if (threadIdx.x < (unsigned)count) w[threadIdx.x] = 0;
 }
 
+// Largest LCP[r] whose two suffixes start in different sequences. A
+// workgroup takes kCrossItems * 256 consecutive ranks; each thread loads its
+// LCP and SA entries (and the SA entry one rank below) for all its items
+// before comparing, so the loads overlap.
+constexpr int kCrossItems = 16;
+
 __global__ __launch_bounds__(kBlock) void k_cross_max(const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp,
                                                       uint32_t n, SeqStarts st, uint32_t *__restrict__ out_max) {
     __shared__ int32_t s_start[kMaxSeqs + 1];
     __shared__ int32_t s_red[kBlock / kWave];
     for (int i = threadIdx.x; i <= st.k; i += kBlock) s_start[i] = st.start[i];
     __syncthreads();
-    int32_t best = 0;
-    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x + 1; r < n; r += gridDim.x * kBlock) {
-        const int32_t v = lcp[r];
-        if (v > best && seq_of(s_start, st.k, sa[r - 1]) != seq_of(s_start, st.k, sa[r])) best = v;
+    const uint32_t r0 = blockIdx.x * (kBlock * kCrossItems) + threadIdx.x + 1;
+    int32_t v[kCrossItems], a[kCrossItems], b[kCrossItems];
+#pragma unroll
+    for (int j = 0; j < kCrossItems; ++j) {
+        const uint32_t r = r0 + j * kBlock;
+        const bool ok = r < n;
+        v[j] = ok ? lcp[r] : 0;
+        a[j] = ok ? sa[r - 1] : 0;
+        b[j] = ok ? sa[r] : 0;
     }
+    int32_t best = 0;
+#pragma unroll
+    for (int j = 0; j < kCrossItems; ++j)
+        if (v[j] > best && seq_of(s_start, st.k, a[j]) != seq_of(s_start, st.k, b[j])) best = v[j];
     for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o, 64));
     if ((threadIdx.x & 63u) == 0) s_red[threadIdx.x >> 6] = best;
     __syncthreads();
     if (threadIdx.x == 0) {
-        int32_t b = s_red[0];
-        for (int i = 1; i < kBlock / kWave; ++i) b = max(b, s_red[i]);
-        if (b > 0) atomicMax(out_max, (uint32_t)b);
+        int32_t m = s_red[0];
+        for (int i = 1; i < kBlock / kWave; ++i) m = max(m, s_red[i]);
+        if (m > 0) atomicMax(out_max, (uint32_t)m);
     }
 }
 
@@ -239,7 +254,8 @@ lor_status overlap_scan(const int32_t *sa, const int32_t *lcp, uint32_t n, const
     if (n < 2) return LOR_OK;
     LOR_LAUNCH("k_init", 0, s, hipLaunchKernelGGL(k_init, dim3(1), dim3(kBlock), 0, s, words, 4));
     LOR_LAUNCH("k_cross_max", (double)n * 8, s,
-               hipLaunchKernelGGL(k_cross_max, dim3(grid_for(n)), dim3(kBlock), 0, s, sa, lcp, n, st, words));
+               hipLaunchKernelGGL(k_cross_max, dim3(div_up(n - 1, kBlock * kCrossItems)), dim3(kBlock), 0, s, sa, lcp,
+                                  n, st, words));
     uint32_t L = 0;
     LOR_HIP(hipMemcpyAsync(&L, words, 4, hipMemcpyDeviceToHost, s));
     LOR_HIP(hipStreamSynchronize(s));
