@@ -669,7 +669,7 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
             LOR_LAUNCH("k_name_write", (double)d.m * 12, s,
                        hipLaunchKernelGGL(k_name_write<uint64_t>, dim3(G), dim3(kBlock), 0, s, kc, d.m, G, gcount,
                                           names));
-            LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, names, 0, d.m, tmp4, counts, s));
+            LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, names, 0, d.m, tmp4, counts, s, true));
         }
     } else {
         uint32_t *k0, *k1, *aux, *aux2;
@@ -701,7 +701,7 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
             LOR_LAUNCH("k_name_write", (double)d.m * 8, s,
                        hipLaunchKernelGGL(k_name_write<uint32_t>, dim3(G), dim3(kBlock), 0, s, kc, d.m, G, gcount,
                                           names));
-            LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, names, 0, d.m, tmp4, counts, s));
+            LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, names, 0, d.m, tmp4, counts, s, true));
         }
     }
 
@@ -753,7 +753,7 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
         uint32_t *tb[4], *cr;
         for (int i = 0; i < 4; ++i) LOR_TAKE(ar, uint32_t, d.m, tb[i]);
         LOR_TAKE(ar, uint32_t, radix_counts_words(d.m), cr);
-        if (run) LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, nullptr, 1, d.m, tb, cr, s));
+        if (run) LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, nullptr, 1, d.m, tb, cr, s, true));
         ar.release(mk);
     }
     const int32_t *rank12 = R;
@@ -788,7 +788,7 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
                    hipLaunchKernelGGL(k_ns_pairs<CH>, dim3(grid_for(d.n0)), dim3(kBlock), 0, s, t, d, rank12, keys0,
                                       vals0));
         uint32_t *const tmp4[4] = {keys1, vals1, sc0, sc1};
-        LOR_TRY(bucketed_scatter(R, d.m, keys0, vals0, 0, d.n0, tmp4, counts2, s));
+        LOR_TRY(bucketed_scatter(R, d.m, keys0, vals0, 0, d.n0, tmp4, counts2, s, false));
         const uint32_t G = scan_groups(d.m);
         LOR_LAUNCH("k_ns_count", (double)d.m * 4, s,
                    hipLaunchKernelGGL(k_ns_count, dim3(G), dim3(kBlock), 0, s, sa12, d, G, gcount2));

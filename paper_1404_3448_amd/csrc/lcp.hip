@@ -146,7 +146,7 @@ lor_status lcp_build_t(const CH *text, uint32_t n, const int32_t *sa, int32_t *l
     // both 8-byte buffers are free again: four n-word scatter buffers
     uint32_t *k32 = reinterpret_cast<uint32_t *>(keys), *k232 = reinterpret_cast<uint32_t *>(keys2);
     uint32_t *const tmp4[4] = {k32, k32 + n, k232, k232 + n};
-    return bucketed_scatter(lcp, n, reinterpret_cast<const uint32_t *>(isa_w), plcp, 0, n, tmp4, counts, s);
+    return bucketed_scatter(lcp, n, reinterpret_cast<const uint32_t *>(isa_w), plcp, 0, n, tmp4, counts, s, true);
 }
 
 lor_status lcp_build(const uint8_t *text, uint32_t n, const int32_t *sa, int32_t *lcp, int32_t *isa, Arena &ar,

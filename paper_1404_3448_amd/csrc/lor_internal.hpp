@@ -99,8 +99,9 @@ void set_decision_tape(DecisionTape *tape);   // for the calling thread; nullptr
 DecisionTape *decision_tape();
 void set_capturing(bool on);                  // no event timing while a stream is captured
 
-// Device count of compute units (queried once per device).
-int num_cus();
+// Largest LDS allocation one workgroup may take on the current device
+// (queried once per device).
+size_t max_lds_per_block();
 
 // ------------------------------------------------------------------ plan
 // Tuning knobs chosen by the autotuner. A plan changes speed, never results.
@@ -191,8 +192,12 @@ struct BucketDigits {
     int lo_shift, lo_bits;   // the digit below it (lo_bits == 0: none)
 };
 BucketDigits bucket_digits(uint32_t dst_n);
+// permutation: idx holds every value of 0..dst_n-1 exactly once (n == dst_n);
+// the last kernel then writes whole windows of dst from LDS.
 lor_status bucketed_scatter(int32_t *dst, uint32_t dst_n, const uint32_t *idx, const uint32_t *val, uint32_t voff,
-                            uint32_t n, uint32_t *const tmp[4], uint32_t *counts, hipStream_t s);
+                            uint32_t n, uint32_t *const tmp[4], uint32_t *counts, hipStream_t s, bool permutation);
+// Window (entries) of the permutation store for a destination of dst_n entries.
+uint32_t scatter_window(uint32_t dst_n);
 
 // ------------------------------------------------------------- device scan
 // Exclusive scan of `count` u32 block totals in place (one workgroup);
