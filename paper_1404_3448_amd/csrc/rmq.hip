@@ -5,10 +5,10 @@
 // The paper answers RMQ through a Cartesian tree, an Euler tour and +-1RMQ.
 // Here the structure is a sparse table: level k holds the minimum of every
 // window of 2^k LCP entries, and a query reads two overlapping windows that
-// cover its range. Levels 1-10 are built five at a time: a workgroup loads a
-// tile of level k0-1 plus the halo the next five levels reach into, and
-// computes and writes those levels from LDS, so level k0-1 is read once for
-// five levels. Higher levels (windows wider than a tile) are built one at a
+// cover its range. Levels 1-10 are built in one pass: a workgroup loads a
+// tile of the LCP array plus the halo the ten levels reach into, and
+// computes and writes those levels from LDS, so the LCP array is read once
+// for ten levels. Higher levels (windows wider than a tile) are built one at a
 // time from level k-1 (two streaming reads, one write per entry; tiles are
 // ordered so that most entries are fetched from HBM once). With 288 GB of HBM the table fits next to
 // the 1G-suffix arrays, and every query costs four independent gathers
@@ -58,7 +58,8 @@ __global__ __launch_bounds__(kBlock) void k_st_level(const int32_t *__restrict__
 }
 
 constexpr uint32_t kStTile = kBlock * 16;   // outputs per workgroup in fused levels
-constexpr int kStFuse = 5;                  // levels per fused pass
+constexpr int kStFuse = 10;                 // levels per fused pass
+constexpr int kStFusedTop = 10;             // levels 1..10 are built in LDS (halo < 1024 entries)
 
 __device__ __forceinline__ uint64_t level_offset_dev(uint64_t n, int level);
 
@@ -163,8 +164,8 @@ uint64_t rmq_level_offset(uint64_t n, int level) {
 
 lor_status rmq_build_levels(const int32_t *lcp, uint32_t n, int32_t *table, int levels, hipStream_t s) {
     int k = 1;
-    while (k <= levels && k <= 2 * kStFuse) {
-        const int nl = min(kStFuse, levels - k + 1);
+    while (k <= levels && k <= kStFusedTop) {
+        const int nl = min(kStFuse, min(levels, kStFusedTop) - k + 1);
         const int32_t *prev = k == 1 ? lcp : table + rmq_level_offset(n, k - 1);
         const uint32_t prev_count = n - (1u << (k - 1)) + 1u;
         const uint32_t count = n - (1u << k) + 1u;
