@@ -114,16 +114,28 @@ lor_status lor_build_lcp(const uint8_t *text, int64_t n, const int32_t *sa,
  * array itself and is not copied. The table memory is caller-owned; the
  * handle is plain data that records where the levels are. */
 typedef struct {
-    int32_t *table;      /* device memory holding levels 1..levels */
+    int32_t *table;      /* device memory holding the levels */
     int64_t n;           /* length of the LCP array */
-    int32_t levels;      /* floor(log2 n), 0 when n < 2 */
-    int32_t reserved;
+    int32_t levels;      /* full: floor(log2 n), 0 when n < 2; compact: see below */
+    int32_t kind;        /* 0: full sparse table, 1: compact block table */
 } lor_rmq;
 
 /* Bytes of levels 1..floor(log2 n). */
 size_t lor_rmq_bytes(int64_t n);
 lor_status lor_rmq_build(const int32_t *lcp, int64_t n, void *table, size_t table_bytes,
                          lor_rmq *out, void *hip_stream);
+
+/* Low-memory variant: the same structure over the minima of 64-entry blocks
+ * of LCP. Level 0 holds the nb = ceil(n / 64) block minima and level k
+ * (1 <= k <= levels = floor(log2 nb)) the minimum of every run of 2^k
+ * blocks: about 4 (n / 64) log2(n / 64) bytes instead of 4 n log2 n (1.6 GB
+ * instead of 120 GB at n = 2^30). A query scans the partial blocks at the
+ * ends of its range in LCP and reads the whole blocks between them from
+ * the table. lor_rmq_query answers through such a handle with the same
+ * values and the same leftmost positions as through a full table. */
+size_t lor_rmq_compact_bytes(int64_t n);
+lor_status lor_rmq_compact_build(const int32_t *lcp, int64_t n, void *table, size_t table_bytes,
+                                 lor_rmq *out, void *hip_stream);
 
 /* Batched queries, one result per query k < nq:
  *  mode 0 (rank ranges): lo = qi[k], hi = qj[k], 0 <= lo <= hi < n;
@@ -136,8 +148,8 @@ lor_status lor_rmq_build(const int32_t *lcp, int64_t n, void *table, size_t tabl
  *         argmin_out (nullable) receives the rank of that minimum.
  * A query whose indices fall outside 0..n-1 (or lo > hi in mode 0) yields
  * -1 in both outputs and is otherwise ignored.
- * lcp must be the array the handle was built from; a handle with a different
- * n returns LOR_ESTALE. */
+ * lcp must be the array the handle was built from; a handle whose n, kind
+ * or level count do not match a built table returns LOR_ESTALE. */
 lor_status lor_rmq_query(const lor_rmq *rmq, const int32_t *lcp, const int32_t *isa, int32_t mode,
                          const int32_t *qi, const int32_t *qj, int64_t nq,
                          int32_t *min_out, int32_t *argmin_out, void *hip_stream);

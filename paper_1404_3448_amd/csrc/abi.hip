@@ -344,7 +344,37 @@ lor_status lor_rmq_build(const int32_t *lcp, int64_t n, void *table, size_t tabl
     out->table = static_cast<int32_t *>(table);
     out->n = n;
     out->levels = levels;
-    out->reserved = 0;
+    out->kind = 0;
+    return LOR_OK;
+}
+
+size_t lor_rmq_compact_bytes(int64_t n) {
+    if (n < 1 || n > INT32_MAX) return 0;
+    return (size_t)rmq_compact_entries((uint64_t)n, nullptr) * sizeof(int32_t);
+}
+
+lor_status lor_rmq_compact_build(const int32_t *lcp, int64_t n, void *table, size_t table_bytes, lor_rmq *out,
+                                 void *hip_stream) {
+    if (!out || n < 0 || n > INT32_MAX || (n > 0 && !lcp)) {
+        set_error("invalid RMQ build arguments");
+        return LOR_EINVAL;
+    }
+    const size_t need = lor_rmq_compact_bytes(n);
+    if (need && (!table || !aligned(table, 4))) {
+        set_error("RMQ table NULL or misaligned");
+        return LOR_EINVAL;
+    }
+    if (table_bytes < need) {
+        set_error("RMQ table of %zu bytes, %zu needed", table_bytes, need);
+        return LOR_EWORKSPACE;
+    }
+    int levels = 0;
+    if (n > 0) rmq_compact_entries((uint64_t)n, &levels);
+    LOR_TRY(rmq_build_compact(lcp, (uint32_t)n, static_cast<int32_t *>(table), (hipStream_t)hip_stream));
+    out->table = static_cast<int32_t *>(table);
+    out->n = n;
+    out->levels = levels;
+    out->kind = 1;
     return LOR_OK;
 }
 
@@ -360,8 +390,22 @@ lor_status lor_rmq_query(const lor_rmq *rmq, const int32_t *lcp, const int32_t *
         set_error("NULL query array");
         return LOR_EINVAL;
     }
+    if (rmq->n < 1 || rmq->n > INT32_MAX || (rmq->kind != 0 && rmq->kind != 1)) {
+        set_error("RMQ handle does not describe a built table");
+        return LOR_ESTALE;
+    }
+    if (rmq->kind == 1) {
+        int expect = 0;
+        rmq_compact_entries((uint64_t)rmq->n, &expect);
+        if (rmq->levels != expect || !rmq->table) {
+            set_error("RMQ handle does not describe a built table");
+            return LOR_ESTALE;
+        }
+        return rmq_queries_compact(rmq->table, (uint32_t)rmq->n, rmq->levels, lcp, isa, mode, qi, qj, (uint32_t)nq,
+                                   min_out, argmin_out, (hipStream_t)hip_stream);
+    }
     const int expect = rmq->n >= 2 ? bits_for((uint64_t)rmq->n) - 1 : 0;
-    if (rmq->n < 1 || rmq->n > INT32_MAX || rmq->levels != expect || (expect > 0 && !rmq->table)) {
+    if (rmq->levels != expect || (expect > 0 && !rmq->table)) {
         set_error("RMQ handle does not describe a built table");
         return LOR_ESTALE;
     }

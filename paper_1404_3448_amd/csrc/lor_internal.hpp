@@ -239,6 +239,14 @@ lor_status lcp_build_u16(const uint16_t *text, uint32_t n, const int32_t *sa, in
 // ------------------------------------------------------------------ RMQ
 uint64_t rmq_level_offset(uint64_t n, int level);   // entries before `level` (levels from 1)
 lor_status rmq_build_levels(const int32_t *lcp, uint32_t n, int32_t *table, int levels, hipStream_t s);
+// Compact table: block minima of 64-entry blocks, then levels 1..levels
+// over the blocks. Entries in total (and the level count via *levels).
+uint64_t rmq_compact_blocks(uint64_t n);
+uint64_t rmq_compact_entries(uint64_t n, int *levels);
+lor_status rmq_build_compact(const int32_t *lcp, uint32_t n, int32_t *table, hipStream_t s);
+lor_status rmq_queries_compact(const int32_t *table, uint32_t n, int levels, const int32_t *lcp, const int32_t *isa,
+                               int mode, const int32_t *qi, const int32_t *qj, uint32_t nq, int32_t *min_out,
+                               int32_t *argmin_out, hipStream_t s);
 lor_status rmq_queries(const int32_t *table, uint32_t n, int levels, const int32_t *lcp,
                        const int32_t *isa, int mode, const int32_t *qi, const int32_t *qj,
                        uint32_t nq, int32_t *min_out, int32_t *argmin_out, hipStream_t s);

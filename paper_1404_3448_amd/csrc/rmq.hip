@@ -60,6 +60,7 @@ __global__ __launch_bounds__(kBlock) void k_st_level(const int32_t *__restrict__
 constexpr uint32_t kStTile = kBlock * 16;   // outputs per workgroup in fused levels
 constexpr int kStFuse = 10;                 // levels per fused pass
 constexpr int kStFusedTop = 10;             // levels 1..10 are built in LDS (halo < 1024 entries)
+constexpr uint32_t kRmqBlock = 64;          // LCP entries per block of the compact table
 
 __device__ __forceinline__ uint64_t level_offset_dev(uint64_t n, int level);
 
@@ -155,7 +156,143 @@ __global__ __launch_bounds__(kBlock) void k_query(Levels L, const int32_t *__res
     }
 }
 
+// ------------------------------------------------------ compact variant
+// A sparse table over the minima of kRmqBlock-entry blocks of LCP (level 0 =
+// the block minima, levels 1.. over blocks), about 4 n / 64 * log2(n / 64)
+// bytes instead of 4 n log2 n. A query scans the partial blocks at its two
+// ends in LCP itself and takes the whole blocks between them from the table.
+
+struct Compact {
+    const int32_t *lcp;
+    const int32_t *table;
+    uint32_t n, nb;
+    int levels;
+};
+
+__device__ __forceinline__ const int32_t *clevel(const Compact &C, int k) {
+    return k == 0 ? C.table : C.table + C.nb + level_offset_dev(C.nb, k);
+}
+
+// Smallest value of lcp[a..b] (a <= b) and its leftmost position.
+__device__ __forceinline__ int32_t scan_min(const int32_t *__restrict__ lcp, uint32_t a, uint32_t b, uint32_t *pos) {
+    int32_t best = INT_MAX;
+    uint32_t bp = a;
+    for (uint32_t x = a; x <= b; ++x) {
+        const int32_t y = lcp[x];
+        if (y < best) {
+            best = y;
+            bp = x;
+        }
+    }
+    *pos = bp;
+    return best;
+}
+
+__device__ int32_t range_min_compact(const Compact &C, uint32_t lo, uint32_t hi, bool want_pos, int32_t *pos) {
+    const uint32_t bl = lo / kRmqBlock, bh = hi / kRmqBlock;
+    uint32_t p;
+    if (bh - bl <= 1) {
+        const int32_t v = scan_min(C.lcp, lo, hi, &p);
+        *pos = (int32_t)p;
+        return v;
+    }
+    uint32_t pl, pr;
+    const int32_t vl = scan_min(C.lcp, lo, (bl + 1) * kRmqBlock - 1, &pl);
+    const int32_t vr = scan_min(C.lcp, bh * kRmqBlock, hi, &pr);
+    const uint32_t a = bl + 1, c = bh - 1;   // whole blocks in between
+    const int k = 31 - __builtin_clz(c - a + 1);
+    const int32_t *lv = clevel(C, k);
+    const int32_t vm = min(lv[a], lv[c + 1 - (1u << k)]);
+    const int32_t v = min(vl, min(vm, vr));
+    if (want_pos) {
+        if (vl == v) {
+            *pos = (int32_t)pl;
+        } else if (vm == v) {
+            uint32_t b = a;   // leftmost block whose minimum is v
+            for (int kk = k; kk >= 0; --kk) {
+                const uint32_t w = 1u << kk;
+                if (b + w - 1 <= c && clevel(C, kk)[b] > v) b += w;
+            }
+            uint32_t x = b * kRmqBlock;
+            const uint32_t xe = x + kRmqBlock - 1;   // the block holds v; bounded all the same
+            while (x < xe && C.lcp[x] != v) ++x;
+            *pos = (int32_t)x;
+        } else {
+            *pos = (int32_t)pr;
+        }
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_block_min(const int32_t *__restrict__ lcp, uint32_t n, uint32_t nb,
+                                                      int32_t *__restrict__ bmin) {
+    const uint32_t b = (blockIdx.x * kBlock + threadIdx.x) / kWave, lane = threadIdx.x & 63u;
+    if (b >= nb) return;   // whole waves
+    const uint32_t i = b * kRmqBlock + lane;
+    int32_t v = i < n ? lcp[i] : INT_MAX;
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    if (lane == 0) bmin[b] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_query_compact(Compact C, const int32_t *__restrict__ isa, int mode,
+                                                          const int32_t *__restrict__ qi,
+                                                          const int32_t *__restrict__ qj, uint32_t nq,
+                                                          int32_t *__restrict__ out_min,
+                                                          int32_t *__restrict__ out_arg) {
+    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < nq; q += gridDim.x * kBlock) {
+        const int32_t a = qi[q], b = qj[q];
+        int32_t v = -1, pos = -1;
+        if (mode == 0) {
+            if (a >= 0 && b >= a && (uint32_t)b < C.n)
+                v = range_min_compact(C, (uint32_t)a, (uint32_t)b, out_arg != nullptr, &pos);
+        } else if (a >= 0 && b >= 0 && (uint32_t)a < C.n && (uint32_t)b < C.n) {
+            if (a == b) {
+                v = (int32_t)(C.n - (uint32_t)a);
+            } else {
+                const int32_t ra = isa[a], rb = isa[b];
+                if (ra != rb && (uint32_t)ra < C.n && (uint32_t)rb < C.n) {
+                    const uint32_t lo = (uint32_t)min(ra, rb) + 1u, hi = (uint32_t)max(ra, rb);
+                    v = range_min_compact(C, lo, hi, out_arg != nullptr, &pos);
+                }
+            }
+        }
+        out_min[q] = v;
+        if (out_arg) out_arg[q] = pos;
+    }
+}
+
 }  // namespace
+
+uint64_t rmq_compact_blocks(uint64_t n) { return (n + kRmqBlock - 1) / kRmqBlock; }
+
+uint64_t rmq_compact_entries(uint64_t n, int *levels) {
+    const uint64_t nb = rmq_compact_blocks(n);
+    const int L = nb >= 2 ? bits_for(nb) - 1 : 0;
+    if (levels) *levels = L;
+    return nb + (L ? rmq_level_offset(nb, L + 1) : 0);
+}
+
+lor_status rmq_build_compact(const int32_t *lcp, uint32_t n, int32_t *table, hipStream_t s) {
+    if (n == 0) return LOR_OK;
+    int L;
+    rmq_compact_entries(n, &L);
+    const uint32_t nb = (uint32_t)rmq_compact_blocks(n);
+    LOR_LAUNCH("k_block_min", 4.0 * n + 4.0 * nb, s,
+               hipLaunchKernelGGL(k_block_min, dim3(div_up((uint64_t)nb * kWave, kBlock)), dim3(kBlock), 0, s, lcp,
+                                  n, nb, table));
+    return rmq_build_levels(table, nb, table + nb, L, s);
+}
+
+lor_status rmq_queries_compact(const int32_t *table, uint32_t n, int levels, const int32_t *lcp, const int32_t *isa,
+                               int mode, const int32_t *qi, const int32_t *qj, uint32_t nq, int32_t *min_out,
+                               int32_t *argmin_out, hipStream_t s) {
+    if (nq == 0) return LOR_OK;
+    Compact C{lcp, table, n, (uint32_t)rmq_compact_blocks(n), levels};
+    LOR_LAUNCH("k_query_compact", (double)nq * (mode ? 28 : 20), s,
+               hipLaunchKernelGGL(k_query_compact, dim3(grid_for(nq)), dim3(kBlock), 0, s, C, isa, mode, qi, qj, nq,
+                                  min_out, argmin_out));
+    return LOR_OK;
+}
 
 uint64_t rmq_level_offset(uint64_t n, int level) {
     const uint64_t k = (uint64_t)level - 1;

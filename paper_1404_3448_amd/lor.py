@@ -36,7 +36,7 @@ class LorError(RuntimeError):
 
 class lor_rmq(ctypes.Structure):
     _fields_ = [("table", ctypes.c_void_p), ("n", ctypes.c_int64), ("levels", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("kind", ctypes.c_int32)]
 
 
 class lor_overlap(ctypes.Structure):
@@ -89,6 +89,8 @@ def lib():
         "lor_rmq_bytes": ([I64], SZ),
         "lor_rmq_build": ([P, I64, P, SZ, ctypes.POINTER(lor_rmq), P], I32),
         "lor_rmq_query": ([ctypes.POINTER(lor_rmq), P, P, I32, P, P, I64, P, P, P], I32),
+        "lor_rmq_compact_bytes": ([I64], SZ),
+        "lor_rmq_compact_build": ([P, I64, P, SZ, ctypes.POINTER(lor_rmq), P], I32),
         "lor_longest_overlap_workspace": ([I64, I32], SZ),
         "lor_longest_overlap": ([P, P, I64, P, I32, ctypes.POINTER(lor_overlap), P, SZ, P], I32),
         "lor_longest_overlap_batched_workspace": ([I64, I32], SZ),
@@ -238,7 +240,8 @@ def lor_build_lcp(text, sa, lcp_out=None, isa_out=None, want_isa=False, ws=None,
 # -------------------------------------------------------------------- RMQ
 
 class Rmq:
-    """A built sparse table: the C handle plus the tensor that owns its memory."""
+    """A built sparse table (full or compact): the C handle plus the tensor
+    that owns its memory."""
 
     def __init__(self, handle: lor_rmq, table):
         self.handle = handle
@@ -252,9 +255,17 @@ class Rmq:
     def levels(self):
         return int(self.handle.levels)
 
+    @property
+    def compact(self) -> bool:
+        return int(self.handle.kind) == 1
+
 
 def lor_rmq_bytes(n: int) -> int:
     return int(lib().lor_rmq_bytes(n))
+
+
+def lor_rmq_compact_bytes(n: int) -> int:
+    return int(lib().lor_rmq_compact_bytes(n))
 
 
 def lor_rmq_build(lcp, table=None, stream=None) -> Rmq:
@@ -268,6 +279,20 @@ def lor_rmq_build(lcp, table=None, stream=None) -> Rmq:
     st = lib().lor_rmq_build(_ptr(lcp), n, _ptr(table), table.numel() * table.element_size(), ctypes.byref(h),
                              _stream(stream))
     _check("lor_rmq_build", st)
+    return Rmq(h, table)
+
+
+def lor_rmq_compact_build(lcp, table=None, stream=None) -> Rmq:
+    import torch
+    n = lcp.numel()
+    _need(lcp, torch.int32, n, "lcp")
+    nbytes = lor_rmq_compact_bytes(n)
+    if table is None:
+        table = torch.empty(max(nbytes // 4, 1), dtype=torch.int32, device=lcp.device)
+    h = lor_rmq()
+    st = lib().lor_rmq_compact_build(_ptr(lcp), n, _ptr(table), table.numel() * table.element_size(),
+                                     ctypes.byref(h), _stream(stream))
+    _check("lor_rmq_compact_build", st)
     return Rmq(h, table)
 
 

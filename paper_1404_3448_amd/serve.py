@@ -11,7 +11,8 @@ follow-up suffix-pair lcp queries) arrive over time. The loop
   and memory free up and their kernels overlap on the device;
 * coalesces small requests into mini-batches for the batched entry point and
   runs large requests (and every request that keeps state) on the plain path;
-* keeps SA-derived state resident for the requests that ask for it, answers
+* keeps SA-derived state resident for the requests that ask for it (LCP,
+  ISA and the compact block sparse table, about 8.4 bytes per base), answers
   their follow-up query batch when it arrives, then frees it;
 * records arrival-to-result latency per request and per follow-up batch.
 
@@ -67,14 +68,15 @@ def plain_bytes(total_bases: int, keep: bool) -> int:
              lor.lor_longest_overlap_workspace(n, 2))
     b = total_bases + n + 4 * n * 2 + ws          # seqs, joined, sa, lcp, workspace
     if keep:
-        b += 4 * n + lor.lor_rmq_bytes(n)         # isa + sparse table stay resident
+        b += 4 * n + lor.lor_rmq_compact_bytes(n)   # isa + compact sparse table stay resident
     return int(b)
 
 
 def resident_bytes(total_bases: int) -> int:
-    """Bytes that stay after a keep-state request: LCP, ISA, sparse table."""
+    """Bytes that stay after a keep-state request: LCP, ISA and the compact
+    (block) sparse table."""
     n = total_bases + 2
-    return int(4 * n * 2 + lor.lor_rmq_bytes(n))
+    return int(4 * n * 2 + lor.lor_rmq_compact_bytes(n))
 
 
 def batch_bytes(total_bases: int, pairs: int) -> int:
@@ -112,7 +114,7 @@ class GpuRunner:
             ov = lor.lor_longest_overlap(sa, lcp, req.offsets, stream=s)
             state = None
             if req.keep:
-                rmq = lor.lor_rmq_build(lcp, stream=s)
+                rmq = lor.lor_rmq_compact_build(lcp, stream=s)
                 state = {"lcp": lcp, "isa": isa, "rmq": rmq}
             s.synchronize()
         return ov, state

@@ -130,3 +130,23 @@ def test_graph_argument_errors(L):
     assert L.lor_longest_overlap_batched_graph_status(None, None) == lor.LOR_EINVAL
     assert L.lor_longest_overlap_batched_graph_levels(None) == -1
     L.lor_longest_overlap_batched_graph_destroy(None)
+
+
+def test_rmq_compact_sizes_and_handles(L):
+    def expect(n):
+        nb = -(-n // 64)
+        levels = nb.bit_length() - 1 if nb >= 2 else 0
+        return 4 * (nb + sum(nb - (1 << k) + 1 for k in range(1, levels + 1)))
+    for n in (1, 2, 63, 64, 65, 129, 4097, 100003, (1 << 30) + 16, (1 << 31) - 1):
+        assert lor.lor_rmq_compact_bytes(n) == expect(n), n
+    assert lor.lor_rmq_compact_bytes(0) == 0
+    n = (1 << 30) + 16
+    assert lor.lor_rmq_compact_bytes(n) * 60 < lor.lor_rmq_bytes(n)       # the point of the variant
+    h = lor.lor_rmq()
+    assert L.lor_rmq_compact_build(FAKE, 100, FAKE, 8, ctypes.byref(h), None) == lor.LOR_EWORKSPACE
+    h.n, h.table, h.kind = 100000, 1 << 20, 1
+    h.levels = 3                                    # ceil(100000/64) = 1563 blocks: 10 levels
+    assert L.lor_rmq_query(ctypes.byref(h), FAKE, FAKE, 0, FAKE, FAKE, 5, FAKE, None, None) == lor.LOR_ESTALE
+    h.kind = 2
+    h.levels = 10
+    assert L.lor_rmq_query(ctypes.byref(h), FAKE, FAKE, 0, FAKE, FAKE, 5, FAKE, None, None) == lor.LOR_ESTALE

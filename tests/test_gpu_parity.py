@@ -239,7 +239,8 @@ def test_tiny_pair_workload():
 # ------------------------------------------------------------------- RMQ
 
 @pytest.mark.parametrize("n_bases", [3, 17, 1000, 40000])
-def test_rmq_range_and_pair_queries(n_bases):
+@pytest.mark.parametrize("compact", [False, True])
+def test_rmq_range_and_pair_queries(n_bases, compact):
     rng = np.random.default_rng(n_bases)
     w = synth.noncoding_pair(seed=n_bases, n=n_bases, segments=2, seg_lo=2, seg_hi=max(3, n_bases // 3))
     d = dev(w.concat)
@@ -247,8 +248,13 @@ def test_rmq_range_and_pair_queries(n_bases):
     joined = oracle.join(w.concat, w.offsets)
     n = joined.size
     lcp_h = host(r["lcp"])
-    rmq = lor.lor_rmq_build(r["lcp"])
-    assert rmq.levels == n.bit_length() - 1
+    if compact:
+        rmq = lor.lor_rmq_compact_build(r["lcp"])
+        nb = -(-n // 64)
+        assert rmq.compact and rmq.levels == (nb.bit_length() - 1 if nb >= 2 else 0)
+    else:
+        rmq = lor.lor_rmq_build(r["lcp"])
+        assert rmq.levels == n.bit_length() - 1
     lo = rng.integers(0, n, size=3000)
     hi = np.minimum(n - 1, lo + rng.integers(0, n, size=3000) % (1 + rng.integers(1, n + 1, size=3000)))
     mn, am = lor.lor_rmq_query(rmq, r["lcp"], r["isa"], 0, dev(lo.astype(np.int32)), dev(hi.astype(np.int32)),
@@ -325,3 +331,27 @@ def test_long_text_1g_full_size():
     pick = rng.choice(w.queries[0].size, size=20000, replace=False)
     want = oracle.pair_queries(joined_h, w.queries[0][pick], w.queries[1][pick])
     assert np.array_equal(got_h[pick], want)
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 127, 128, 129, 191, 1000, 4097, 100003])
+@pytest.mark.parametrize("values", [2, 50, 1 << 20])
+def test_rmq_compact_equals_oracle_and_full_table(n, values):
+    """Compact (block) table: values and leftmost positions equal the plain
+    minimum and the full table's, for ranges inside a block, across a block
+    boundary and spanning many blocks; few distinct values make ties common."""
+    say("rmq compact", n, values)
+    rng = np.random.default_rng(n * 31 + values)
+    lcp_h = rng.integers(0, values, size=n).astype(np.int32)
+    lcp = dev(lcp_h)
+    full = lor.lor_rmq_build(lcp) if n >= 1 else None
+    comp = lor.lor_rmq_compact_build(lcp)
+    lo = rng.integers(0, n, size=4000)
+    span = np.where(rng.random(4000) < 0.5, rng.integers(0, 130, size=4000), rng.integers(0, n, size=4000))
+    hi = np.minimum(n - 1, lo + span)
+    lo_d, hi_d = dev(lo.astype(np.int32)), dev(hi.astype(np.int32))
+    mc, ac = lor.lor_rmq_query(comp, lcp, None, 0, lo_d, hi_d, want_argmin=True)
+    mf, af = lor.lor_rmq_query(full, lcp, None, 0, lo_d, hi_d, want_argmin=True)
+    mc, ac, mf, af = host(mc), host(ac), host(mf), host(af)
+    assert np.array_equal(mc, mf) and np.array_equal(ac, af)
+    for k in range(0, lo.size, 7):
+        assert (mc[k], ac[k]) == oracle.range_min(lcp_h, lo[k], hi[k])

@@ -79,5 +79,5 @@ def test_byte_accounting_matches_size_queries():
     n = 1000 + 2
     ws = max(lor.lor_build_sa_workspace(1000, 2), lor.lor_build_lcp_workspace(n), lor.lor_longest_overlap_workspace(n, 2))
     assert serve.plain_bytes(1000, False) == 1000 + n + 8 * n + ws
-    assert serve.plain_bytes(1000, True) - serve.plain_bytes(1000, False) == 4 * n + lor.lor_rmq_bytes(n)
-    assert serve.resident_bytes(1000) == 8 * n + lor.lor_rmq_bytes(n)
+    assert serve.plain_bytes(1000, True) - serve.plain_bytes(1000, False) == 4 * n + lor.lor_rmq_compact_bytes(n)
+    assert serve.resident_bytes(1000) == 8 * n + lor.lor_rmq_compact_bytes(n)
