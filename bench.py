@@ -341,6 +341,11 @@ def main():
     log(f"compact RMQ: {rmq_compact}")
     del ctab, cout, crmq, ws_sa, ws_lcp, ws_ov, joined, sa, lcp, isa, qout, seqs, qi, qj
     torch.cuda.empty_cache()
+    from paper_1404_3448_amd import ablation
+    log("radix ablation (digit width, size alignment) ...")
+    abl = ablation.run()
+    log(f"ablation: {abl}")
+
     batched = None
     if not args.no_batched:
         log("batched vs plain loop ...")
@@ -387,6 +392,7 @@ def main():
         "batched": batched,
         "serving": serving,
         "rmq_compact": rmq_compact,
+        "radix_ablation": abl,
         "cpu_baseline": cpu,
         "paper_context": {"claim": "more than 20x over a serial CPU run (abstract, Section I)",
                           "hardware": "Intel Core i3-3110M host, GeForce 610M",

@@ -245,7 +245,7 @@ lor_status lor_sort_pairs_u64(uint64_t *keys, uint32_t *vals, int64_t n, int32_t
 /* --------------------------------------------------------------- tuning
  * Tuning knobs of the kernels, chosen by the autotuner
  * (paper_1404_3448_amd/autotune.py). A plan changes speed, never results.
- *   digit_bits       radix digit width, 4..8 (Section IV's radix sort takes
+ *   digit_bits       radix digit width, 1..8 (Section IV's radix sort takes
  *                    one bit per pass; wider digits mean fewer passes)
  *   radix_items_u32  radix tile = 256 threads x items, 32-bit keys: 8|12|16|24
  *   radix_items_u64  same for 64-bit keys: 8|12|16

@@ -80,7 +80,7 @@ bool plan_valid(const Plan &p) {
             if (v == x) return true;
         return false;
     };
-    return p.digit_bits >= 4 && p.digit_bits <= 8 && in(p.items_u32, {8, 12, 16, 24}) &&
+    return p.digit_bits >= 1 && p.digit_bits <= 8 && in(p.items_u32, {8, 12, 16, 24}) &&
            in(p.items_u64, {8, 12, 16}) && in(p.merge_items, {4, 8, 12}) && p.plcp_steps >= 16 &&
            p.plcp_steps <= 1024;
 }

@@ -99,7 +99,7 @@ def test_plan_validation():
     assert lor.lor_plan_get().as_dict() == lor.lor_plan_default().as_dict()
     lor.lor_plan_set({"digit_bits": 6, "merge_items": 4})
     assert lor.lor_plan_get().digit_bits == 6
-    for bad in ({"digit_bits": 9}, {"radix_items_u32": 10}, {"radix_items_u64": 24}, {"radix_items_u64": 4}, {"merge_items": 16},
+    for bad in ({"digit_bits": 9}, {"digit_bits": 0}, {"radix_items_u32": 10}, {"radix_items_u64": 24}, {"radix_items_u64": 4}, {"merge_items": 16},
                 {"plcp_steps": 4}):
         with pytest.raises(lor.LorError):
             lor.lor_plan_set(bad)

@@ -14,6 +14,8 @@ PLANS = [
     dict(digit_bits=6, radix_items_u32=8, radix_items_u64=8, merge_items=4, plcp_steps=16),
     dict(digit_bits=7, radix_items_u32=24, radix_items_u64=16, merge_items=12, plcp_steps=512),
     dict(digit_bits=5, radix_items_u32=12, radix_items_u64=12, merge_items=8, plcp_steps=64),
+    dict(digit_bits=8, radix_items_u32=16, radix_items_u64=16, merge_items=4, plcp_steps=32),   # tuned, gfx950
+    dict(digit_bits=3, radix_items_u32=24, radix_items_u64=12, merge_items=12, plcp_steps=1024),
 ]
 
 
@@ -57,3 +59,23 @@ def test_batched_per_call_plan():
     for p in PLANS[1:]:
         assert lor.records_to_tuples(lor.lor_longest_overlap_batched(d, offs, plan=p)) == base
     assert lor.lor_plan_get().as_dict() == lor.lor_plan_default().as_dict()
+
+
+@pytest.mark.parametrize("digit_bits", [1, 2, 3, 5])
+def test_narrow_digits_sort_identically(digit_bits):
+    """Digits down to the one bit per pass of Section IV give the same stable order."""
+    rng = np.random.default_rng(digit_bits)
+    n = 100003
+    keys = rng.integers(0, 1 << 20, size=n, dtype=np.uint64).astype(np.uint32)
+    keys[rng.random(n) < 0.2] = keys[0]
+    order = np.argsort(keys, kind="stable")
+    saved = lor.lor_plan_get().as_dict()
+    try:
+        lor.lor_plan_set(dict(saved, digit_bits=digit_bits))
+        k = torch.from_numpy(keys.view(np.int32)).cuda()
+        v = torch.arange(n, dtype=torch.int32, device="cuda")
+        lor.lor_sort_pairs_u32(k, v, 0, 20)
+        assert np.array_equal(k.cpu().numpy().view(np.uint32), keys[order])
+        assert np.array_equal(v.cpu().numpy(), order.astype(np.int32))
+    finally:
+        lor.lor_plan_set(saved)
