@@ -178,6 +178,48 @@ def bench_batched(lor, synth, torch, reps: int = 3) -> dict:
             "speedup": round(plain_s / batched_s, 2), "identical_to_plain": batched == plain}
 
 
+def bench_ref_queries(lor, synth, torch, reps: int = 3, loop_sample: int = 256) -> dict:
+    """One 4M-base reference against 65,536 queries (lengths log-uniform in
+    [100, 2000], a third carrying a mutated reference segment; seed 6): one
+    call over all queries versus the plain per-pair path on a sample."""
+    t0 = time.perf_counter()
+    w = synth.ref_queries()
+    offs = w.offsets
+    Q = len(w.seqs) - 1
+    log(f"reference vs queries: {Q} queries, {int(offs[-1])} bases, generated in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    d = torch.from_numpy(w.concat).to(dev)
+    out = torch.empty(Q * 32, dtype=torch.uint8, device=dev)
+    ws = torch.empty(lor.lor_longest_overlap_ref_workspace(int(offs[-1]), Q), dtype=torch.uint8, device=dev)
+    lor.lor_longest_overlap_ref(d, offs, out=out, ws=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        lor.lor_longest_overlap_ref(d, offs, out=out, ws=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    recs = lor.records_to_tuples(out)
+    del ws
+    # the plain path, one (query, reference) pair at a time, on a sample
+    ref = w.seqs[0]
+    same = True
+    t = time.perf_counter()
+    for q in range(1, loop_sample + 1):
+        query = w.seqs[q]
+        po = np.array([0, query.size, query.size + ref.size], np.int64)
+        pd = torch.from_numpy(np.concatenate([query, ref])).to(dev)
+        ov = lor.longest_overlap_region(pd, po)["overlap"]
+        same &= recs[q - 1][0] == ov[0] and (ov[0] == 0 or recs[q - 1][2] == ov[2])
+    torch.cuda.synchronize()
+    loop_s = (time.perf_counter() - t) / loop_sample
+    return {"workload": f"reference of {ref.size} bases, {Q} queries of 100..2000 bases (log-uniform), "
+                        f"{int(offs[-1])} bases in total (seed 6)",
+            "queries": Q, "ms": round(1e3 * dt, 3), "queries_per_s": round(Q / dt, 1),
+            "Mbases_per_s": round(int(offs[-1]) / dt / 1e6, 1),
+            "plain_per_query_ms": round(1e3 * loop_s, 3), "speedup_vs_plain_loop": round(loop_s * Q / dt, 1),
+            "plain_sample": loop_sample, "sample_identical_length_and_query_offset": bool(same)}
+
+
 def bench_serving(seed: int = 5) -> dict:
     """Poisson requests (each sequence 1e4..4e6 bases, log-uniform; 30% keep
     state and send 10^4 follow-up queries after an exponential delay of mean
@@ -346,6 +388,10 @@ def main():
     abl = ablation.run()
     log(f"ablation: {abl}")
 
+    log("reference vs queries ...")
+    refq = bench_ref_queries(lor, synth, torch)
+    log(f"reference vs queries: {refq}")
+
     batched = None
     if not args.no_batched:
         log("batched vs plain loop ...")
@@ -393,6 +439,7 @@ def main():
         "serving": serving,
         "rmq_compact": rmq_compact,
         "radix_ablation": abl,
+        "ref_queries": refq,
         "cpu_baseline": cpu,
         "paper_context": {"claim": "more than 20x over a serial CPU run (abstract, Section I)",
                           "hardware": "Intel Core i3-3110M host, GeForce 610M",

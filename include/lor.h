@@ -197,6 +197,25 @@ lor_status lor_longest_overlap_batched(const uint8_t *seqs, const int64_t *offse
                                        const void *plan, lor_overlap *out_device,
                                        void *ws, size_t ws_bytes, void *hip_stream);
 
+/* ------------------------------------- one reference, many query sequences
+ * The shape of the experiments of Section V (a reference group against many
+ * query sequences): for every query, the longest substring it shares with
+ * the reference, from one suffix array over the reference and all queries.
+ * seqs: device uint8 bases (0..3), the reference (sequence 0) and then the
+ * queries 1..num_queries, concatenated; offsets: HOST
+ * int64[num_queries + 2], offsets[0] = 0, non-decreasing (empty sequences
+ * are allowed). The sum of the lengths plus num_queries + 1 must not exceed
+ * 2^31 - 1. out_device: device lor_overlap[num_queries]; record q - 1 holds
+ * the length L of the longest common substring of query q and the
+ * reference, seq_p = q with off_p the smallest offset in the query where a
+ * common substring of length L starts, and seq_q = 0 with off_q an offset
+ * in the reference where that substring occurs. L = 0 gives -1 for the
+ * sequences and offsets. A base outside 0..3 returns LOR_EALPHABET.
+ * Synchronises hip_stream before returning. */
+size_t lor_longest_overlap_ref_workspace(int64_t total_bases, int32_t num_queries);
+lor_status lor_longest_overlap_ref(const uint8_t *seqs, const int64_t *offsets, int32_t num_queries,
+                                   lor_overlap *out_device, void *ws, size_t ws_bytes, void *hip_stream);
+
 /* ----------------------------------- batched longest overlap, HIP graph
  * The batched call captured once as a HIP graph and replayed. The graph is
  * bound to seqs, offsets (copied into pinned host memory it owns), plan,

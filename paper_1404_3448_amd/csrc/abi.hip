@@ -645,6 +645,44 @@ int32_t lor_longest_overlap_batched_graph_levels(const lor_batched_graph *graph)
 
 void lor_longest_overlap_batched_graph_destroy(lor_batched_graph *graph) { free_graph(graph); }
 
+size_t lor_longest_overlap_ref_workspace(int64_t total_bases, int32_t num_queries) {
+    if (total_bases < 0 || num_queries < 1 || total_bases + (int64_t)num_queries + 1 > INT32_MAX) return 0;
+    return refq_workspace((uint64_t)total_bases, (uint32_t)num_queries);
+}
+
+lor_status lor_longest_overlap_ref(const uint8_t *seqs, const int64_t *offsets, int32_t num_queries,
+                                   lor_overlap *out_device, void *ws, size_t ws_bytes, void *hip_stream) {
+    if (num_queries < 1) {
+        set_error("num_queries %d < 1", num_queries);
+        return LOR_EINVAL;
+    }
+    if (!offsets || !out_device) {
+        set_error("NULL offsets or out_device");
+        return LOR_EINVAL;
+    }
+    if (offsets[0] != 0) {
+        set_error("offsets[0] must be 0");
+        return LOR_EINVAL;
+    }
+    for (int64_t j = 0; j <= (int64_t)num_queries; ++j) {
+        if (offsets[j + 1] < offsets[j]) {
+            set_error("offsets decrease at %lld", (long long)j);
+            return LOR_EINVAL;
+        }
+    }
+    const int64_t total = offsets[num_queries + 1];
+    if (total + (int64_t)num_queries + 1 > INT32_MAX) {
+        set_error("joined length exceeds 2^31-1");
+        return LOR_ETOOLARGE;
+    }
+    if (total > 0 && !seqs) {
+        set_error("seqs is NULL");
+        return LOR_EINVAL;
+    }
+    LOR_TRY(check_ws(ws, ws_bytes, lor_longest_overlap_ref_workspace(total, num_queries)));
+    return refq_overlap(seqs, offsets, (uint32_t)num_queries, out_device, ws, ws_bytes, (hipStream_t)hip_stream);
+}
+
 size_t lor_sort_pairs_workspace(int64_t n, int32_t key_bytes) {
     if (n < 0 || n > INT32_MAX || (key_bytes != 4 && key_bytes != 8)) return 0;
     return kHeaderBytes + 1024 + (size_t)n * (size_t)(key_bytes + 4) + radix_counts_words((uint64_t)n) * 4;

@@ -271,6 +271,11 @@ uint64_t batch_tables(const int64_t *offsets, uint32_t num_pairs, int32_t *h_sta
 lor_status batch_overlap_run(const uint8_t *seqs, uint32_t num_pairs, uint64_t N, const int32_t *h_start,
                              const int32_t *h_alen, const int64_t *h_src, lor_overlap *out, void *ws,
                              size_t ws_bytes, hipStream_t s);
+// ---------------------------------------------- reference against queries
+size_t refq_workspace(uint64_t total_bases, uint32_t num_queries);
+lor_status refq_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t num_queries, lor_overlap *out,
+                        void *ws, size_t ws_bytes, hipStream_t s);
+
 lor_status overlap_scan(const int32_t *sa, const int32_t *lcp, uint32_t n, const SeqStarts &st,
                         Arena &ar, hipStream_t s, int64_t result[5]);
 

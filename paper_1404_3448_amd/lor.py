@@ -95,6 +95,8 @@ def lib():
         "lor_longest_overlap": ([P, P, I64, P, I32, ctypes.POINTER(lor_overlap), P, SZ, P], I32),
         "lor_longest_overlap_batched_workspace": ([I64, I32], SZ),
         "lor_longest_overlap_batched": ([P, P, I32, P, P, P, SZ, P], I32),
+        "lor_longest_overlap_ref_workspace": ([I64, I32], SZ),
+        "lor_longest_overlap_ref": ([P, P, I32, P, P, SZ, P], I32),
         "lor_longest_overlap_batched_graph_create": ([P, P, I32, P, P, P, SZ, P, ctypes.POINTER(P)], I32),
         "lor_longest_overlap_batched_graph_launch": ([P, P], I32),
         "lor_longest_overlap_batched_graph_status": ([P, P], I32),
@@ -359,6 +361,29 @@ def lor_longest_overlap_batched(seqs, offsets, out=None, ws=None, stream=None, p
     st = lib().lor_longest_overlap_batched(_ptr(seqs), o.ctypes.data_as(ctypes.c_void_p), P, pl, _ptr(out),
                                            _ptr(ws), ws.numel() * ws.element_size(), _stream(stream))
     _check("lor_longest_overlap_batched", st)
+    return out
+
+
+def lor_longest_overlap_ref_workspace(total_bases: int, num_queries: int) -> int:
+    return int(lib().lor_longest_overlap_ref_workspace(total_bases, num_queries))
+
+
+def lor_longest_overlap_ref(seqs, offsets, out=None, ws=None, stream=None):
+    """Longest substring every query (sequences 1..Q) shares with the
+    reference (sequence 0). Returns the device lor_overlap records as bytes
+    (see records_to_tuples)."""
+    import torch
+    o = _offsets(offsets)
+    Q = o.size - 2
+    if Q < 1:
+        raise ValueError("offsets: need int64[num_queries + 2] with num_queries >= 1")
+    _need(seqs, torch.uint8, int(o[-1]), "seqs")
+    if out is None:
+        out = torch.empty(Q * ctypes.sizeof(lor_overlap), dtype=torch.uint8, device=seqs.device)
+    ws = _workspace(lor_longest_overlap_ref_workspace(int(o[-1]), Q), seqs.device, ws)
+    st = lib().lor_longest_overlap_ref(_ptr(seqs), o.ctypes.data_as(ctypes.c_void_p), Q, _ptr(out), _ptr(ws),
+                                       ws.numel() * ws.element_size(), _stream(stream))
+    _check("lor_longest_overlap_ref", st)
     return out
 
 

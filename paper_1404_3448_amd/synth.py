@@ -188,6 +188,30 @@ def batched_pairs(seed: int = 4, num_pairs: int = 4096, lo: float = 1e3, hi: flo
     return out
 
 
+def ref_queries(seed: int = 6, ref_len: int = 1 << 22, num_queries: int = 1 << 16, lo: float = 100,
+                hi: float = 2000) -> Workload:
+    """One noncoding-like reference and many noncoding-like queries (the
+    shape of Section V: a reference group against many query sequences).
+    Query lengths are log-uniform in [lo, hi]; every third query carries a
+    segment copied from the reference (length log-uniform in [20, q/2],
+    1% point mutations) at a uniform position. seqs[0] is the reference."""
+    rng = rng_for(seed)
+    ref = noncoding_like(rng, ref_len)
+    seqs = [ref]
+    planted = []
+    for i in range(num_queries):
+        n = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        q = noncoding_like(rng, n)
+        if i % 3 == 0 and n >= 40:
+            length = int(round(math.exp(rng.uniform(math.log(20), math.log(n / 2)))))
+            s = int(rng.integers(0, ref_len - length))
+            p = int(rng.integers(0, n - length + 1))
+            q[p:p + length] = mutate(rng, ref[s:s + length].copy(), 0.01)
+            planted.append((i + 1, p, s, length))
+        seqs.append(q)
+    return Workload("ref_queries", seqs, planted)
+
+
 def random_text(seed: int, n: int, alphabet: int = 4) -> np.ndarray:
     """iid uniform codes in [0, alphabet) for small test cases."""
     return rng_for(seed).integers(0, alphabet, size=n, dtype=np.uint8)

@@ -150,3 +150,18 @@ def test_rmq_compact_sizes_and_handles(L):
     h.kind = 2
     h.levels = 10
     assert L.lor_rmq_query(ctypes.byref(h), FAKE, FAKE, 0, FAKE, FAKE, 5, FAKE, None, None) == lor.LOR_ESTALE
+
+
+def test_ref_queries_argument_errors(L):
+    o, op = offsets(0, 10, 14, 20)        # reference + 2 queries
+    ws = lor.lor_longest_overlap_ref_workspace(20, 2)
+    assert ws > 0
+    assert L.lor_longest_overlap_ref(FAKE, op, 0, FAKE, FAKE, ws, None) == lor.LOR_EINVAL
+    bad, bp = offsets(0, 10, 9, 20)
+    assert L.lor_longest_overlap_ref(FAKE, bp, 2, FAKE, FAKE, ws, None) == lor.LOR_EINVAL
+    assert L.lor_longest_overlap_ref(FAKE, op, 2, None, FAKE, ws, None) == lor.LOR_EINVAL
+    assert L.lor_longest_overlap_ref(FAKE, op, 2, FAKE, FAKE, ws - 1, None) == lor.LOR_EWORKSPACE
+    big, gp = offsets(0, 1 << 30, (1 << 31) - 2, (1 << 31) - 2)
+    assert L.lor_longest_overlap_ref(FAKE, gp, 2, FAKE, FAKE, ws, None) == lor.LOR_ETOOLARGE
+    assert lor.lor_longest_overlap_ref_workspace(-1, 2) == 0
+    assert lor.lor_longest_overlap_ref_workspace(20, 0) == 0
