@@ -361,6 +361,24 @@ def main():
                     "launch_ms_avg": round(dom["ms"] / dom["launches"], 4),
                     "alg_bytes_per_launch_avg": round(dom["bytes"] / dom["launches"])}
 
+    # all-pairs overlap matrix of the 16 sequences, on the same SA and LCP
+    mout = torch.empty(num_seqs * num_seqs * 32, dtype=torch.uint8, device=dev)
+    mws = torch.empty(lor.lor_overlap_matrix_workspace(N, num_seqs), dtype=torch.uint8, device=dev)
+    lor.lor_overlap_matrix(sa, lcp, offsets, out=mout, ws=mws)
+    torch.cuda.synchronize()
+    t_m = time.perf_counter()
+    lor.lor_overlap_matrix(sa, lcp, offsets, out=mout, ws=mws)
+    torch.cuda.synchronize()
+    t_m = time.perf_counter() - t_m
+    mrec = lor.records_to_tuples(mout)
+    mat_L = [[mrec[a * num_seqs + b][0] for b in range(num_seqs)] for a in range(num_seqs)]
+    matrix = {"sequences": num_seqs, "ms": round(1e3 * t_m, 3),
+              "max_equals_longest_overlap": max(max(r) for r in mat_L) == ov[0],
+              "symmetric": all(mat_L[a][b] == mat_L[b][a] for a in range(num_seqs) for b in range(num_seqs)),
+              "lengths": mat_L}
+    log(f"overlap matrix: {num_seqs}x{num_seqs} in {matrix['ms']} ms, max {max(max(r) for r in mat_L)}")
+    del mout, mws
+
     # the low-memory (block) table on the same LCP, the same queries
     del table
     torch.cuda.empty_cache()
@@ -438,6 +456,7 @@ def main():
         "batched": batched,
         "serving": serving,
         "rmq_compact": rmq_compact,
+        "overlap_matrix": matrix,
         "radix_ablation": abl,
         "ref_queries": refq,
         "cpu_baseline": cpu,

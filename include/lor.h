@@ -197,6 +197,23 @@ lor_status lor_longest_overlap_batched(const uint8_t *seqs, const int64_t *offse
                                        const void *plan, lor_overlap *out_device,
                                        void *ws, size_t ws_bytes, void *hip_stream);
 
+/* --------------------------------------------------- all-pairs overlap
+ * The longest overlap region of every pair of different sequences of one
+ * joined text (lor_build_sa's layout), from its SA and LCP: a num_seqs x
+ * num_seqs matrix of records. Record a * num_seqs + b (a != b) holds the
+ * length L of the longest substring sequences a and b share, seq_p = a with
+ * off_p the smallest offset in a where such a substring starts, and
+ * seq_q = b with off_q an offset in b where it occurs; L = 0 and the
+ * diagonal give -1 for the sequences and offsets. The maximum over the
+ * matrix is the length lor_longest_overlap reports.
+ * sa, lcp: device int32[n]; offsets: host int64[num_seqs + 1] as in
+ * lor_build_sa (n must equal offsets[num_seqs] + num_seqs); out_device:
+ * device lor_overlap[num_seqs * num_seqs]. Synchronises hip_stream. */
+size_t lor_overlap_matrix_workspace(int64_t n, int32_t num_seqs);
+lor_status lor_overlap_matrix(const int32_t *sa, const int32_t *lcp, int64_t n, const int64_t *offsets,
+                              int32_t num_seqs, lor_overlap *out_device, void *ws, size_t ws_bytes,
+                              void *hip_stream);
+
 /* ------------------------------------- one reference, many query sequences
  * The shape of the experiments of Section V (a reference group against many
  * query sequences): for every query, the longest substring it shares with

@@ -683,6 +683,34 @@ lor_status lor_longest_overlap_ref(const uint8_t *seqs, const int64_t *offsets, 
     return refq_overlap(seqs, offsets, (uint32_t)num_queries, out_device, ws, ws_bytes, (hipStream_t)hip_stream);
 }
 
+size_t lor_overlap_matrix_workspace(int64_t n, int32_t num_seqs) {
+    if (n < 0 || n > INT32_MAX || num_seqs < 1 || num_seqs > kMaxSeqs) return 0;
+    return matrix_workspace((uint64_t)n, (uint32_t)num_seqs);
+}
+
+lor_status lor_overlap_matrix(const int32_t *sa, const int32_t *lcp, int64_t n, const int64_t *offsets,
+                              int32_t num_seqs, lor_overlap *out_device, void *ws, size_t ws_bytes,
+                              void *hip_stream) {
+    int64_t N = 0;
+    LOR_TRY(check_offsets(offsets, num_seqs, &N));
+    if (N != n) {
+        set_error("n = %lld does not match the joined length %lld", (long long)n,
+                  (long long)(offsets[num_seqs] + num_seqs));
+        return LOR_EINVAL;
+    }
+    if (n > 0 && (!sa || !lcp)) {
+        set_error("NULL sa or lcp");
+        return LOR_EINVAL;
+    }
+    if (!out_device) {
+        set_error("NULL out_device");
+        return LOR_EINVAL;
+    }
+    LOR_TRY(check_ws(ws, ws_bytes, lor_overlap_matrix_workspace(n, num_seqs)));
+    return overlap_matrix(sa, lcp, (uint32_t)n, offsets, (uint32_t)num_seqs, out_device, ws, ws_bytes,
+                          (hipStream_t)hip_stream);
+}
+
 size_t lor_sort_pairs_workspace(int64_t n, int32_t key_bytes) {
     if (n < 0 || n > INT32_MAX || (key_bytes != 4 && key_bytes != 8)) return 0;
     return kHeaderBytes + 1024 + (size_t)n * (size_t)(key_bytes + 4) + radix_counts_words((uint64_t)n) * 4;

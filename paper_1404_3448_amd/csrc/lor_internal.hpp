@@ -275,6 +275,10 @@ lor_status batch_overlap_run(const uint8_t *seqs, uint32_t num_pairs, uint64_t N
 size_t refq_workspace(uint64_t total_bases, uint32_t num_queries);
 lor_status refq_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t num_queries, lor_overlap *out,
                         void *ws, size_t ws_bytes, hipStream_t s);
+// All-pairs matrix over an existing SA/LCP of the joined text of k sequences.
+size_t matrix_workspace(uint64_t n, uint32_t k);
+lor_status overlap_matrix(const int32_t *sa, const int32_t *lcp, uint32_t n, const int64_t *offsets, uint32_t k,
+                          lor_overlap *out, void *ws, size_t ws_bytes, hipStream_t s);
 
 lor_status overlap_scan(const int32_t *sa, const int32_t *lcp, uint32_t n, const SeqStarts &st,
                         Arena &ar, hipStream_t s, int64_t result[5]);

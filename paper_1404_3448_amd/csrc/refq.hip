@@ -84,13 +84,18 @@ struct RankItem {
     bool ref;
 };
 
+// Target sequence: joined positions [tlo, thi) (its separator at thi).
+struct Target {
+    uint32_t lo, hi, seq;
+};
+
 __device__ __forceinline__ RankItem rank_item(const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp,
-                                              uint32_t n, uint32_t ref_len, uint32_t r) {
+                                              uint32_t n, const Target &tg, uint32_t r) {
     RankItem it{-1, 0, false};
     if (r < n) {
         it.sa = sa[r];
         it.lcp = lcp[r];
-        it.ref = (uint32_t)it.sa < ref_len;
+        it.ref = (uint32_t)it.sa >= tg.lo && (uint32_t)it.sa < tg.hi;
     }
     return it;
 }
@@ -139,7 +144,7 @@ __device__ Bwd block_bwd_excl(Bwd v, Bwd *s) {
 
 // Forward and backward states of every tile of kRqTile ranks.
 __global__ __launch_bounds__(kBlock) void k_rq_tiles(const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp,
-                                                     uint32_t n, uint32_t ref_len, Fwd *__restrict__ tf,
+                                                     uint32_t n, Target tg, Fwd *__restrict__ tf,
                                                      Bwd *__restrict__ tb) {
     __shared__ Fwd s_f[kBlock];
     __shared__ Bwd s_b[kBlock];
@@ -148,11 +153,11 @@ __global__ __launch_bounds__(kBlock) void k_rq_tiles(const int32_t *__restrict__
     Bwd b = b_id();
 #pragma unroll
     for (uint32_t k = 0; k < kRqItems; ++k) {
-        const RankItem it = rank_item(sa, lcp, n, ref_len, c0 + k);
+        const RankItem it = rank_item(sa, lcp, n, tg, c0 + k);
         if (c0 + k < n) f = f_comb(f, f_elem(it, c0 + k));
     }
     for (int k = (int)kRqItems - 1; k >= 0; --k) {
-        const RankItem it = rank_item(sa, lcp, n, ref_len, c0 + k);
+        const RankItem it = rank_item(sa, lcp, n, tg, c0 + k);
         if (c0 + k < n) b = b_comb(b_elem(it, c0 + k), b);
     }
     const Fwd fe = block_fwd_excl<kBlock>(f, s_f);
@@ -187,21 +192,22 @@ __global__ __launch_bounds__(kRqScanThreads) void k_rq_tile_scan(Fwd *__restrict
     }
 }
 
-// Per rank: the credited match of every query suffix. emit == 0: fold it
-// into best[query] = max(m << 32 | ~offset). emit == 1: the rank that holds
-// its query's best writes the record.
+// Per rank: the credited match of every suffix of another sequence j with
+// the target. emit == 0: fold it into best[j * stride + base] =
+// max(m << 32 | ~offset). emit == 1: the rank that holds its slot's best
+// writes the record.
 __global__ __launch_bounds__(kBlock) void k_rq_ranks(const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp,
-                                                     uint32_t n, uint32_t ref_len, const int32_t *__restrict__ start,
+                                                     uint32_t n, Target tg, const int32_t *__restrict__ start,
                                                      uint32_t S, const Fwd *__restrict__ pre,
-                                                     const Bwd *__restrict__ post, int emit,
-                                                     unsigned long long *__restrict__ best,
+                                                     const Bwd *__restrict__ post, int emit, uint32_t stride,
+                                                     int32_t base, unsigned long long *__restrict__ best,
                                                      lor_overlap *__restrict__ out) {
     __shared__ Fwd s_f[kBlock];
     __shared__ Bwd s_b[kBlock];
     const uint32_t c0 = blockIdx.x * kRqTile + threadIdx.x * kRqItems;
     RankItem it[kRqItems];
 #pragma unroll
-    for (uint32_t k = 0; k < kRqItems; ++k) it[k] = rank_item(sa, lcp, n, ref_len, c0 + k);
+    for (uint32_t k = 0; k < kRqItems; ++k) it[k] = rank_item(sa, lcp, n, tg, c0 + k);
     Fwd f = f_id();
     Bwd b = b_id();
 #pragma unroll
@@ -225,25 +231,28 @@ __global__ __launch_bounds__(kBlock) void k_rq_ranks(const int32_t *__restrict__
         const int32_t down_at = bs.first;
         bs = b_comb(b_elem(it[k], r), bs);
         const uint32_t x = (uint32_t)it[k].sa;
-        if (it[k].ref || x == ref_len) continue;   // reference suffix or its separator
+        if (x >= tg.lo && x <= tg.hi) continue;   // target suffix or its separator
         const uint32_t j = seq_at(start, S, x);
-        if (j == 0 || j >= S) continue;
-        const uint32_t d = (uint32_t)start[j + 1] - 1u - x;   // distance to the query's separator
+        if (j >= S || j == tg.seq) continue;
+        const uint32_t d = (uint32_t)start[j + 1] - 1u - x;   // distance to its own separator
         const int32_t m = min(max(up[k], down), (int32_t)d);
         if (m <= 0) continue;
         const uint32_t off = x - (uint32_t)start[j];
         const unsigned long long key = ((unsigned long long)(uint32_t)m << 32) | (0xffffffffu - off);
+        const int64_t slot = (int64_t)j * stride + base;
         if (!emit) {
-            atomicMax(&best[j - 1], key);
-        } else if (best[j - 1] == key) {
+            // best only grows: a stale read can only let a redundant atomic through
+            if (key > __hip_atomic_load(&best[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                atomicMax(&best[slot], key);
+        } else if (best[slot] == key) {
             const int32_t at = up[k] >= down ? up_at[k] : down_at;   // the neighbour that gave m
             lor_overlap rec;
             rec.length = m;
             rec.seq_p = (int32_t)j;
             rec.off_p = off;
-            rec.seq_q = 0;
-            rec.off_q = (at >= 0 && (uint32_t)at < n) ? sa[at] : -1;
-            out[j - 1] = rec;
+            rec.seq_q = (int32_t)tg.seq;
+            rec.off_q = (at >= 0 && (uint32_t)at < n) ? sa[at] - (int32_t)tg.lo : -1;
+            out[slot] = rec;
         }
     }
 }
@@ -282,6 +291,23 @@ lor_status rq_carve(Arena &ar, uint64_t N, uint32_t S, RqLayout *L) {
     return LOR_OK;
 }
 
+// Matches of every other sequence's suffixes with one target sequence:
+// tile states, their scan, then the two per-rank passes.
+lor_status target_scan(const int32_t *sa, const int32_t *lcp, uint32_t n, Target tg, const int32_t *start,
+                       uint32_t S, uint32_t stride, int32_t base, Fwd *tf, Bwd *tb, unsigned long long *best,
+                       lor_overlap *out, hipStream_t s) {
+    const uint32_t tiles = div_up(n, kRqTile);
+    LOR_LAUNCH("k_rq_tiles", 8.0 * n, s,
+               hipLaunchKernelGGL(k_rq_tiles, dim3(tiles), dim3(kBlock), 0, s, sa, lcp, n, tg, tf, tb));
+    LOR_LAUNCH("k_rq_tile_scan", 48.0 * tiles, s,
+               hipLaunchKernelGGL(k_rq_tile_scan, dim3(1), dim3(kRqScanThreads), 0, s, tf, tb, tiles));
+    for (int emit = 0; emit < 2; ++emit)
+        LOR_LAUNCH("k_rq_ranks", 8.0 * n, s,
+                   hipLaunchKernelGGL(k_rq_ranks, dim3(tiles), dim3(kBlock), 0, s, sa, lcp, n, tg, start, S, tf, tb,
+                                      emit, stride, base, best, out));
+    return LOR_OK;
+}
+
 }  // namespace
 
 size_t refq_workspace(uint64_t total_bases, uint32_t num_queries) {
@@ -316,7 +342,6 @@ lor_status refq_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t Q,
     RqLayout L;
     LOR_TRY(rq_carve(ar, N, S, &L));
     const size_t phase = ar.mark();
-    const uint32_t tiles = div_up(N, kRqTile);
 
     LOR_HIP(hipMemcpyAsync(L.start, h_start.data(), (S + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
     LOR_TRY(zero_words(hdr, 16, s));
@@ -330,15 +355,48 @@ lor_status refq_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t Q,
     ar.release(phase);
     LOR_TRY(lcp_build(L.text, (uint32_t)N, L.sa, L.lcp, nullptr, ar, s));
     ar.release(phase);
-    LOR_LAUNCH("k_rq_tiles", 8.0 * N, s,
-               hipLaunchKernelGGL(k_rq_tiles, dim3(tiles), dim3(kBlock), 0, s, L.sa, L.lcp, (uint32_t)N, ref_len,
-                                  L.tf, L.tb));
-    LOR_LAUNCH("k_rq_tile_scan", 48.0 * tiles, s,
-               hipLaunchKernelGGL(k_rq_tile_scan, dim3(1), dim3(kRqScanThreads), 0, s, L.tf, L.tb, tiles));
-    for (int emit = 0; emit < 2; ++emit)
-        LOR_LAUNCH("k_rq_ranks", 8.0 * N, s,
-                   hipLaunchKernelGGL(k_rq_ranks, dim3(tiles), dim3(kBlock), 0, s, L.sa, L.lcp, (uint32_t)N, ref_len,
-                                      L.start, S, L.tf, L.tb, emit, L.best, out));
+    LOR_TRY(target_scan(L.sa, L.lcp, (uint32_t)N, Target{0u, ref_len, 0u}, L.start, S, 1u, -1, L.tf, L.tb, L.best,
+                        out, s));
+    LOR_HIP(hipStreamSynchronize(s));   // the host table must outlive its copy
+    return LOR_OK;
+}
+
+size_t matrix_workspace(uint64_t n, uint32_t k) {
+    const uint32_t tiles = div_up(n ? n : 1, kRqTile);
+    Arena ar;   // measuring
+    ar.top = kHeaderBytes;
+    ar.take<int32_t>((size_t)k + 1);
+    ar.take<unsigned long long>((size_t)k * k);
+    ar.take<Fwd>(tiles);
+    ar.take<Bwd>(tiles);
+    return ar.top + 1024;
+}
+
+lor_status overlap_matrix(const int32_t *sa, const int32_t *lcp, uint32_t n, const int64_t *offsets, uint32_t k,
+                          lor_overlap *out, void *ws, size_t ws_bytes, hipStream_t s) {
+    std::vector<int32_t> h_start(k + 1);
+    for (uint32_t j = 0; j <= k; ++j) h_start[j] = (int32_t)(offsets[j] + j);
+    Arena ar;
+    ar.base = static_cast<char *>(ws);
+    ar.cap = ws_bytes;
+    ar.top = kHeaderBytes;
+    const uint32_t tiles = div_up(n ? n : 1, kRqTile);
+    int32_t *start;
+    unsigned long long *best;
+    Fwd *tf;
+    Bwd *tb;
+    LOR_TAKE(ar, int32_t, (size_t)k + 1, start);
+    LOR_TAKE(ar, unsigned long long, (size_t)k * k, best);
+    LOR_TAKE(ar, Fwd, tiles, tf);
+    LOR_TAKE(ar, Bwd, tiles, tb);
+    LOR_HIP(hipMemcpyAsync(start, h_start.data(), (k + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LOR_LAUNCH("k_rq_init", 40.0 * k * k, s,
+               hipLaunchKernelGGL(k_rq_init, dim3(grid_for((uint64_t)k * k)), dim3(kBlock), 0, s, k * k, best, out));
+    if (n > 0)
+        for (uint32_t t = 0; t < k; ++t) {
+            const Target tg{(uint32_t)h_start[t], (uint32_t)h_start[t + 1] - 1u, t};
+            LOR_TRY(target_scan(sa, lcp, n, tg, start, k, k, (int32_t)t, tf, tb, best, out, s));
+        }
     LOR_HIP(hipStreamSynchronize(s));   // the host table must outlive its copy
     return LOR_OK;
 }

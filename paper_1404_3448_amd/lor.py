@@ -96,6 +96,8 @@ def lib():
         "lor_longest_overlap_batched_workspace": ([I64, I32], SZ),
         "lor_longest_overlap_batched": ([P, P, I32, P, P, P, SZ, P], I32),
         "lor_longest_overlap_ref_workspace": ([I64, I32], SZ),
+        "lor_overlap_matrix_workspace": ([I64, I32], SZ),
+        "lor_overlap_matrix": ([P, P, I64, P, I32, P, P, SZ, P], I32),
         "lor_longest_overlap_ref": ([P, P, I32, P, P, SZ, P], I32),
         "lor_longest_overlap_batched_graph_create": ([P, P, I32, P, P, P, SZ, P, ctypes.POINTER(P)], I32),
         "lor_longest_overlap_batched_graph_launch": ([P, P], I32),
@@ -384,6 +386,28 @@ def lor_longest_overlap_ref(seqs, offsets, out=None, ws=None, stream=None):
     st = lib().lor_longest_overlap_ref(_ptr(seqs), o.ctypes.data_as(ctypes.c_void_p), Q, _ptr(out), _ptr(ws),
                                        ws.numel() * ws.element_size(), _stream(stream))
     _check("lor_longest_overlap_ref", st)
+    return out
+
+
+def lor_overlap_matrix_workspace(n: int, num_seqs: int) -> int:
+    return int(lib().lor_overlap_matrix_workspace(n, num_seqs))
+
+
+def lor_overlap_matrix(sa, lcp, offsets, out=None, ws=None, stream=None):
+    """All-pairs longest overlap of the sequences of one joined text: device
+    lor_overlap records, k x k, row a / column b (see records_to_tuples)."""
+    import torch
+    o = _offsets(offsets)
+    k = o.size - 1
+    n = sa.numel()
+    _need(sa, torch.int32, n, "sa")
+    _need(lcp, torch.int32, n, "lcp")
+    if out is None:
+        out = torch.empty(k * k * ctypes.sizeof(lor_overlap), dtype=torch.uint8, device=sa.device)
+    ws = _workspace(lor_overlap_matrix_workspace(n, k), sa.device, ws)
+    st = lib().lor_overlap_matrix(_ptr(sa), _ptr(lcp), n, o.ctypes.data_as(ctypes.c_void_p), k, _ptr(out), _ptr(ws),
+                                  ws.numel() * ws.element_size(), _stream(stream))
+    _check("lor_overlap_matrix", st)
     return out
 
 

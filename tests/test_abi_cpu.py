@@ -165,3 +165,14 @@ def test_ref_queries_argument_errors(L):
     assert L.lor_longest_overlap_ref(FAKE, gp, 2, FAKE, FAKE, ws, None) == lor.LOR_ETOOLARGE
     assert lor.lor_longest_overlap_ref_workspace(-1, 2) == 0
     assert lor.lor_longest_overlap_ref_workspace(20, 0) == 0
+
+
+def test_matrix_argument_errors(L):
+    o, op = offsets(0, 5, 9)
+    ws = lor.lor_overlap_matrix_workspace(11, 2)
+    assert ws > 0
+    assert L.lor_overlap_matrix(FAKE, FAKE, 12, op, 2, FAKE, FAKE, ws, None) == lor.LOR_EINVAL     # n != 9 + 2
+    assert L.lor_overlap_matrix(FAKE, FAKE, 11, op, 0, FAKE, FAKE, ws, None) == lor.LOR_EINVAL
+    assert L.lor_overlap_matrix(FAKE, FAKE, 11, op, 2, None, FAKE, ws, None) == lor.LOR_EINVAL
+    assert L.lor_overlap_matrix(FAKE, FAKE, 11, op, 2, FAKE, FAKE, ws - 1, None) == lor.LOR_EWORKSPACE
+    assert lor.lor_overlap_matrix_workspace(11, 252) == 0

@@ -1,0 +1,82 @@
+"""All-pairs longest overlap over one joined text: every off-diagonal record
+against the O(nm) DP oracle (length and first offset exactly; the second
+offset must hold the same substring), symmetry of the lengths, and the
+matrix maximum against the single longest overlap."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1404_3448_amd import lor, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def matrix(seqs):
+    offs = np.concatenate([[0], np.cumsum([s.size for s in seqs])]).astype(np.int64)
+    cat = np.concatenate(seqs) if offs[-1] else np.zeros(1, np.uint8)
+    d = torch.from_numpy(np.ascontiguousarray(cat)).cuda()
+    r = lor.longest_overlap_region(d, offs)
+    recs = lor.records_to_tuples(lor.lor_overlap_matrix(r["sa"], r["lcp"], offs))
+    k = len(seqs)
+    return [recs[a * k:(a + 1) * k] for a in range(k)], r["overlap"]
+
+
+def check(seqs):
+    M, single = matrix(seqs)
+    k = len(seqs)
+    for a in range(k):
+        assert M[a][a] == (0, -1, -1, -1, -1)
+        for b in range(k):
+            if a == b:
+                continue
+            L, xa, xb = oracle.lcs_dp(seqs[a], seqs[b])
+            rec = M[a][b]
+            assert rec[0] == L, (a, b, rec, (L, xa, xb))
+            if L == 0:
+                assert rec == (0, -1, -1, -1, -1)
+                continue
+            assert (rec[1], rec[2], rec[3]) == (a, xa, b), (a, b, rec, (L, xa, xb))
+            assert np.array_equal(seqs[b][rec[4]:rec[4] + L], seqs[a][xa:xa + L]), (a, b)
+            assert M[b][a][0] == L
+    assert max(M[a][b][0] for a in range(k) for b in range(k)) == single[0]
+
+
+def test_matrix_closed_forms():
+    check([synth.encode("ATTGCTAC"), synth.encode("GCTA"), synth.encode("CCCC"), np.zeros(0, np.uint8),
+           synth.encode("TTGC")])
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_matrix_random(seed):
+    rng = np.random.default_rng(1200 + seed)
+    k = int(rng.integers(2, 21))
+    alpha = int(rng.integers(1, 5))
+    seqs = [rng.integers(0, alpha, size=int(rng.integers(0, 300)), dtype=np.uint8) for _ in range(k)]
+    for _ in range(k):
+        a, b = rng.integers(0, k, size=2)
+        if a != b and seqs[a].size > 20:
+            s = int(rng.integers(0, seqs[a].size - 10))
+            seg = seqs[a][s:s + int(rng.integers(3, 80))]
+            p = int(rng.integers(0, seqs[b].size + 1))
+            seqs[b] = np.concatenate([seqs[b][:p], seg, seqs[b][p:]])
+    say("matrix", seed, k)
+    check(seqs)
+
+
+def test_matrix_noncoding():
+    rng = synth.rng_for(91)
+    seqs = [synth.noncoding_like(rng, int(rng.integers(1000, 20000))) for _ in range(8)]
+    for i in range(1, 8):
+        s = int(rng.integers(0, seqs[0].size - 600))
+        seg = synth.mutate(rng, seqs[0][s:s + 500].copy(), 0.01)
+        p = int(rng.integers(0, seqs[i].size))
+        seqs[i] = np.concatenate([seqs[i][:p], seg, seqs[i][p:]])
+    check(seqs)
