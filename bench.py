@@ -220,6 +220,44 @@ def bench_ref_queries(lor, synth, torch, reps: int = 3, loop_sample: int = 256) 
             "plain_sample": loop_sample, "sample_identical_length_and_query_offset": bool(same)}
 
 
+def bench_matrix(lor, torch, sa, lcp, offsets, num_seqs, N, ov, dev) -> dict:
+    """All-pairs overlap matrix of the step's sequences, on its SA and LCP."""
+    mout = torch.empty(num_seqs * num_seqs * 32, dtype=torch.uint8, device=dev)
+    mws = torch.empty(lor.lor_overlap_matrix_workspace(N, num_seqs), dtype=torch.uint8, device=dev)
+    lor.lor_overlap_matrix(sa, lcp, offsets, out=mout, ws=mws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    lor.lor_overlap_matrix(sa, lcp, offsets, out=mout, ws=mws)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t
+    rec = lor.records_to_tuples(mout)
+    L = [[rec[a * num_seqs + b][0] for b in range(num_seqs)] for a in range(num_seqs)]
+    return {"sequences": num_seqs, "ms": round(1e3 * t, 3),
+            "max_equals_longest_overlap": max(max(r) for r in L) == ov[0],
+            "symmetric": all(L[a][b] == L[b][a] for a in range(num_seqs) for b in range(num_seqs)),
+            "lengths": L}
+
+
+def bench_rmq_compact(lor, torch, lcp, isa, qi, qj, qout, N, nq, stages, dev) -> dict:
+    """The low-memory (block) table on the step's LCP, with the same queries."""
+    ctab = torch.empty(lor.lor_rmq_compact_bytes(N) // 4, dtype=torch.int32, device=dev)
+    cout = torch.empty(nq, dtype=torch.int32, device=dev)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    crmq = lor.lor_rmq_compact_build(lcp, table=ctab)
+    lor.lor_rmq_query(crmq, lcp, isa, 1, qi, qj, min_out=cout)
+    torch.cuda.synchronize()
+    e0.record()
+    crmq = lor.lor_rmq_compact_build(lcp, table=ctab)
+    e1.record()
+    lor.lor_rmq_query(crmq, lcp, isa, 1, qi, qj, min_out=cout)
+    e2.record()
+    torch.cuda.synchronize()
+    return {"bytes": lor.lor_rmq_compact_bytes(N), "full_table_bytes": lor.lor_rmq_bytes(N),
+            "build_ms": round(e0.elapsed_time(e1), 3), "queries_ms": round(e1.elapsed_time(e2), 3),
+            "full_build_ms": stages["rmq_build"], "full_queries_ms": stages["queries"],
+            "identical_to_full_table": bool(torch.equal(cout, qout))}
+
+
 def bench_serving(seed: int = 5) -> dict:
     """Poisson requests (each sequence 1e4..4e6 bases, log-uniform; 30% keep
     state and send 10^4 follow-up queries after an exponential delay of mean
@@ -251,6 +289,8 @@ def main():
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the overlap matrix, compact RMQ, radix ablation and reference-vs-queries runs")
     ap.add_argument("--calibrate", action="store_true",
                     help="copy 1 GiB device-to-device first (reference for memory counters)")
     args = ap.parse_args()
@@ -361,54 +401,24 @@ def main():
                     "launch_ms_avg": round(dom["ms"] / dom["launches"], 4),
                     "alg_bytes_per_launch_avg": round(dom["bytes"] / dom["launches"])}
 
-    # all-pairs overlap matrix of the 16 sequences, on the same SA and LCP
-    mout = torch.empty(num_seqs * num_seqs * 32, dtype=torch.uint8, device=dev)
-    mws = torch.empty(lor.lor_overlap_matrix_workspace(N, num_seqs), dtype=torch.uint8, device=dev)
-    lor.lor_overlap_matrix(sa, lcp, offsets, out=mout, ws=mws)
-    torch.cuda.synchronize()
-    t_m = time.perf_counter()
-    lor.lor_overlap_matrix(sa, lcp, offsets, out=mout, ws=mws)
-    torch.cuda.synchronize()
-    t_m = time.perf_counter() - t_m
-    mrec = lor.records_to_tuples(mout)
-    mat_L = [[mrec[a * num_seqs + b][0] for b in range(num_seqs)] for a in range(num_seqs)]
-    matrix = {"sequences": num_seqs, "ms": round(1e3 * t_m, 3),
-              "max_equals_longest_overlap": max(max(r) for r in mat_L) == ov[0],
-              "symmetric": all(mat_L[a][b] == mat_L[b][a] for a in range(num_seqs) for b in range(num_seqs)),
-              "lengths": mat_L}
-    log(f"overlap matrix: {num_seqs}x{num_seqs} in {matrix['ms']} ms, max {max(max(r) for r in mat_L)}")
-    del mout, mws
-
-    # the low-memory (block) table on the same LCP, the same queries
+    matrix = rmq_compact = abl = refq = None
     del table
     torch.cuda.empty_cache()
-    ctab = torch.empty(lor.lor_rmq_compact_bytes(N) // 4, dtype=torch.int32, device=dev)
-    cout = torch.empty(nq, dtype=torch.int32, device=dev)
-    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-    crmq = lor.lor_rmq_compact_build(lcp, table=ctab)
-    lor.lor_rmq_query(crmq, lcp, isa, 1, qi, qj, min_out=cout)
-    torch.cuda.synchronize()
-    e0.record()
-    crmq = lor.lor_rmq_compact_build(lcp, table=ctab)
-    e1.record()
-    lor.lor_rmq_query(crmq, lcp, isa, 1, qi, qj, min_out=cout)
-    e2.record()
-    torch.cuda.synchronize()
-    rmq_compact = {"bytes": lor.lor_rmq_compact_bytes(N), "full_table_bytes": lor.lor_rmq_bytes(N),
-                   "build_ms": round(e0.elapsed_time(e1), 3), "queries_ms": round(e1.elapsed_time(e2), 3),
-                   "full_build_ms": stages["rmq_build"], "full_queries_ms": stages["queries"],
-                   "identical_to_full_table": bool(torch.equal(cout, qout))}
-    log(f"compact RMQ: {rmq_compact}")
-    del ctab, cout, crmq, ws_sa, ws_lcp, ws_ov, joined, sa, lcp, isa, qout, seqs, qi, qj
+    if not args.no_extras:
+        matrix = bench_matrix(lor, torch, sa, lcp, offsets, num_seqs, N, ov, dev)
+        log(f"overlap matrix: {num_seqs}x{num_seqs} in {matrix['ms']} ms")
+        rmq_compact = bench_rmq_compact(lor, torch, lcp, isa, qi, qj, qout, N, nq, stages, dev)
+        log(f"compact RMQ: {rmq_compact}")
+    del ws_sa, ws_lcp, ws_ov, joined, sa, lcp, isa, qout, seqs, qi, qj
     torch.cuda.empty_cache()
-    from paper_1404_3448_amd import ablation
-    log("radix ablation (digit width, size alignment) ...")
-    abl = ablation.run()
-    log(f"ablation: {abl}")
-
-    log("reference vs queries ...")
-    refq = bench_ref_queries(lor, synth, torch)
-    log(f"reference vs queries: {refq}")
+    if not args.no_extras:
+        from paper_1404_3448_amd import ablation
+        log("radix ablation (digit width, size alignment) ...")
+        abl = ablation.run()
+        log(f"ablation: {abl}")
+        log("reference vs queries ...")
+        refq = bench_ref_queries(lor, synth, torch)
+        log(f"reference vs queries: {refq}")
 
     batched = None
     if not args.no_batched:
