@@ -35,7 +35,7 @@ namespace {
 
 constexpr int kScanItems = 8;                         // consecutive items per thread in scan-emit kernels
 constexpr uint32_t kScanTile = kBlock * kScanItems;
-constexpr uint32_t kMaxScanGroups = 1024;
+constexpr uint32_t kMaxScanGroups = 4096;
 
 struct Dims {
     uint32_t n, n0, n1, n2, m, dummy;
@@ -202,42 +202,47 @@ __global__ __launch_bounds__(kBlock) void k_name_count(const K *__restrict__ key
 }
 
 // names[r] = 1-based name of sorted entry r (written in sorted order; a
-// bucketed scatter then moves each name to its R-index).
+// bucketed scatter then moves each name to its R-index). Tiles go through
+// LDS so that the per-thread runs of consecutive entries cost coalesced
+// loads and stores.
 template <typename K>
 __global__ __launch_bounds__(kBlock) void k_name_write(const K *__restrict__ keys, uint32_t m, uint32_t groups,
                                                        const uint32_t *__restrict__ counts,
                                                        uint32_t *__restrict__ names) {
     __shared__ uint32_t s_tmp[kBlock / kWave];
+    __shared__ K s_key[kScanTile + 1];      // s_key[1 + l] = keys[g0 + l]; s_key[0] = its predecessor
+    __shared__ uint32_t s_name[kScanTile];
     uint32_t t0, t1;
     group_tiles(m, groups, blockIdx.x, &t0, &t1);
     uint32_t base = counts[blockIdx.x];
     for (uint32_t tile = t0; tile < t1; ++tile) {
-        const uint32_t r0 = tile * kScanTile + threadIdx.x * kScanItems;
+        const uint32_t g0 = tile * kScanTile;
+        for (uint32_t l = threadIdx.x; l <= kScanTile; l += kBlock) {
+            const uint32_t r = g0 + l;   // keys[r - 1] lands in s_key[l]
+            s_key[l] = (r >= 1 && r - 1 < m) ? keys[r - 1] : K(0);
+        }
+        __syncthreads();
+        const uint32_t l0 = threadIdx.x * kScanItems;
         bool f[kScanItems];
         uint32_t c = 0;
-        K prev = (r0 > 0 && r0 < m) ? keys[r0 - 1] : K(0);
 #pragma unroll
         for (int i = 0; i < kScanItems; ++i) {
-            const uint32_t r = r0 + i;
-            f[i] = false;
-            if (r < m) {
-                const K cur = keys[r];
-                f[i] = (r == 0) || cur != prev;
-                prev = cur;
-            }
+            const uint32_t r = g0 + l0 + i;
+            f[i] = r < m && (r == 0 || s_key[l0 + i + 1] != s_key[l0 + i]);
             c += f[i];
         }
         uint32_t tot;
         uint32_t name = base + dev::block_exclusive_sum(c, s_tmp, &tot);
 #pragma unroll
         for (int i = 0; i < kScanItems; ++i) {
-            const uint32_t r = r0 + i;
-            if (r < m) {
-                name += f[i];
-                names[r] = name;
-            }
+            name += f[i];
+            s_name[l0 + i] = name;
         }
+        __syncthreads();
+        for (uint32_t l = threadIdx.x; l < kScanTile; l += kBlock)
+            if (g0 + l < m) names[g0 + l] = s_name[l];
         base += tot;
+        __syncthreads();   // the next tile reuses the LDS
     }
 }
 
@@ -293,6 +298,134 @@ __global__ __launch_bounds__(kBlock) void k_name_table(const CH *__restrict__ t,
         const uint32_t key = triple_key(t, d, b, idx);
         const uint32_t w = min(key >> 5, words - 1);
         R[idx] = (int32_t)(below[w] + (uint32_t)__popc(bitmap[w] & ((1u << (key & 31u)) - 1u)) + 1u);
+    }
+}
+
+// Byte and int32 texts: the code of a triple is mixed-radix in A = alphabet
+// + 1 (symbols are 0..alphabet), (s0 A + s1) A + s2, which keeps the order
+// and equality of the triples in a code space of A^3 instead of 2^(3b); at
+// the second level (97 symbols) the bitmap then fits in LDS. Each thread
+// takes four consecutive q: sample positions 3q+1 (R-index q) and 3q+2
+// (R-index n0 + q) for q in [q0, q0 + 4) need the 16 symbols from 3 q0,
+// read as whole words while the window lies inside the text.
+constexpr uint32_t kWinQ = 4;
+constexpr int kTblBlock = 1024;
+
+template <typename CH>
+__device__ __forceinline__ void sym_window(const CH *t, uint32_t n, uint32_t p0, uint32_t s[16]) {
+    if (p0 + 16u <= n) {
+        if constexpr (sizeof(CH) == 1) {
+            const uint32_t *w = reinterpret_cast<const uint32_t *>(t + p0);   // p0 = 12 g: 4-byte aligned
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t x = w[i];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) s[4 * i + j] = ((x >> (8 * j)) & 255u) + 1u;
+            }
+        } else {
+            const uint4 *w = reinterpret_cast<const uint4 *>(t + p0);        // p0 = 12 g words: 16-byte aligned
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint4 x = w[i];
+                s[4 * i] = x.x; s[4 * i + 1] = x.y; s[4 * i + 2] = x.z; s[4 * i + 3] = x.w;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) s[i] = sym(t, n, p0 + i);
+    }
+}
+
+__device__ __forceinline__ uint32_t mixed_code(uint32_t a, uint32_t b, uint32_t c, uint32_t A) {
+    return (a * A + b) * A + c;
+}
+
+// Codes of the (up to) eight sample triples of group g; ok bits say which exist.
+template <typename CH>
+__device__ __forceinline__ void group_codes(const CH *t, const Dims &d, uint32_t A, uint32_t g, uint32_t c1[kWinQ],
+                                            uint32_t c2[kWinQ]) {
+    uint32_t s[16];
+    sym_window<CH>(t, d.n, 3u * kWinQ * g, s);
+#pragma unroll
+    for (int j = 0; j < (int)kWinQ; ++j) {
+        c1[j] = mixed_code(s[3 * j + 1], s[3 * j + 2], s[3 * j + 3], A);
+        c2[j] = mixed_code(s[3 * j + 2], s[3 * j + 3], s[3 * j + 4], A);
+    }
+}
+
+__device__ __forceinline__ void mark_present(uint32_t *bits, uint32_t words, uint32_t code) {
+    const uint32_t w = code >> 5, bit = 1u << (code & 31u);
+    if (w < words && !(bits[w] & bit)) atomicOr(&bits[w], bit);   // a stale read only costs a redundant atomic
+}
+
+template <typename CH, bool IN_LDS>
+__global__ __launch_bounds__(kTblBlock) void k_presence_w(const CH *__restrict__ t, Dims d, uint32_t A,
+                                                          uint32_t *__restrict__ bitmap, uint32_t words) {
+    extern __shared__ uint32_t s_bits[];
+    if (IN_LDS) {
+        for (uint32_t w = threadIdx.x; w < words; w += kTblBlock) s_bits[w] = 0;
+        __syncthreads();
+    }
+    uint32_t *bits = IN_LDS ? s_bits : bitmap;
+    const uint32_t groups = (d.n0 + kWinQ - 1) / kWinQ;   // n0 >= n2
+    for (uint32_t g = blockIdx.x * kTblBlock + threadIdx.x; g < groups; g += gridDim.x * kTblBlock) {
+        uint32_t c1[kWinQ], c2[kWinQ];
+        group_codes<CH>(t, d, A, g, c1, c2);
+#pragma unroll
+        for (int j = 0; j < (int)kWinQ; ++j) {
+            const uint32_t q = kWinQ * g + j;
+            if (q < d.n0) mark_present(bits, words, c1[j]);
+            if (q < d.n2) mark_present(bits, words, c2[j]);
+        }
+    }
+    if (IN_LDS) {
+        __syncthreads();
+        for (uint32_t w = threadIdx.x; w < words; w += kTblBlock)
+            if (s_bits[w]) atomicOr(&bitmap[w], s_bits[w]);
+    }
+}
+
+// name = 1 + number of present codes below the code. In LDS the table keeps
+// the bitmap and the exclusive count at every fourth word.
+__device__ __forceinline__ uint32_t table_name(const uint32_t *bits, const uint32_t *below4, uint32_t words,
+                                               uint32_t code) {
+    const uint32_t w = min(code >> 5, words - 1);
+    uint32_t c = below4[w >> 2];
+    for (uint32_t u = w & ~3u; u < w; ++u) c += (uint32_t)__popc(bits[u]);
+    return c + (uint32_t)__popc(bits[w] & ((1u << (code & 31u)) - 1u)) + 1u;
+}
+
+template <typename CH>
+__global__ __launch_bounds__(kTblBlock) void k_name_table_w(const CH *__restrict__ t, Dims d, uint32_t A,
+                                                            const uint32_t *__restrict__ bitmap,
+                                                            const uint32_t *__restrict__ below, uint32_t words,
+                                                            int in_lds, int32_t *__restrict__ R) {
+    extern __shared__ uint32_t s_tab[];
+    const uint32_t quads = (words + 3u) / 4u;
+    if (in_lds) {
+        for (uint32_t w = threadIdx.x; w < words; w += kTblBlock) s_tab[w] = bitmap[w];
+        for (uint32_t g = threadIdx.x; g < quads; g += kTblBlock) s_tab[words + g] = below[4u * g];
+        __syncthreads();
+    }
+    const uint32_t groups = (d.n0 + kWinQ - 1) / kWinQ;
+    for (uint32_t g = blockIdx.x * kTblBlock + threadIdx.x; g < groups; g += gridDim.x * kTblBlock) {
+        uint32_t c1[kWinQ], c2[kWinQ];
+        group_codes<CH>(t, d, A, g, c1, c2);
+#pragma unroll
+        for (int j = 0; j < (int)kWinQ; ++j) {
+            const uint32_t q = kWinQ * g + j;
+            uint32_t n1, n2;
+            if (in_lds) {
+                n1 = table_name(s_tab, s_tab + words, words, c1[j]);
+                n2 = table_name(s_tab, s_tab + words, words, c2[j]);
+            } else {
+                const uint32_t w1 = min(c1[j] >> 5, words - 1), w2 = min(c2[j] >> 5, words - 1);
+                n1 = below[w1] + (uint32_t)__popc(bitmap[w1] & ((1u << (c1[j] & 31u)) - 1u)) + 1u;
+                n2 = below[w2] + (uint32_t)__popc(bitmap[w2] & ((1u << (c2[j] & 31u)) - 1u)) + 1u;
+            }
+            if (q < d.n0) R[q] = (int32_t)n1;
+            if (q < d.n2) R[d.n0 + q] = (int32_t)n2;
+        }
     }
 }
 
@@ -417,39 +550,64 @@ __global__ __launch_bounds__(kBlock) void k_ns_pairs(const CH *__restrict__ t, D
 }
 
 // Emit mod-0 position 3*idx (predecessor of mod-1 entry idx) with key
-// t_{3 idx}, which first[r] holds for sample-order slot r.
+// t_{3 idx}, which first[r] holds for sample-order slot r. A tile is staged
+// in LDS: coalesced loads, the order-keeping compaction per thread reads
+// LDS, and the compacted pairs leave as coalesced stores.
 __global__ __launch_bounds__(kBlock) void k_ns_write(const int32_t *__restrict__ first, const int32_t *__restrict__ sa12,
                                                      Dims d, uint32_t groups,
                                                      const uint32_t *__restrict__ counts,
                                                      uint32_t *__restrict__ keys0,
                                                      uint32_t *__restrict__ vals0) {
     __shared__ uint32_t s_tmp[kBlock / kWave];
+    __shared__ __align__(16) uint32_t s_idx[kScanTile];
+    __shared__ __align__(16) uint32_t s_first[kScanTile];
+    __shared__ uint32_t s_k[kScanTile];
+    __shared__ uint32_t s_v[kScanTile];
     uint32_t t0, t1;
     group_tiles(d.m, groups, blockIdx.x, &t0, &t1);
     uint32_t base = counts[blockIdx.x];
     for (uint32_t tile = t0; tile < t1; ++tile) {
-        const uint32_t r0 = tile * kScanTile + threadIdx.x * kScanItems;
-        uint32_t idx[kScanItems];
-        uint32_t c = 0;
+        const uint32_t g0 = tile * kScanTile;
 #pragma unroll
         for (int i = 0; i < kScanItems; ++i) {
-            const uint32_t r = r0 + i;
-            idx[i] = r < d.m ? (uint32_t)sa12[r] : 0xffffffffu;
-            c += idx[i] < d.n0;
+            const uint32_t l = i * kBlock + threadIdx.x, r = g0 + l;
+            const uint32_t x = r < d.m ? (uint32_t)sa12[r] : 0xffffffffu;
+            s_idx[l] = x;
+            s_first[l] = x < d.n0 ? (uint32_t)first[r] : 0u;
         }
+        __syncthreads();
+        const uint32_t l0 = threadIdx.x * kScanItems;
+        uint32_t idx[kScanItems], fs[kScanItems];
+#pragma unroll
+        for (int h = 0; h < kScanItems / 4; ++h) {
+            const uint4 a = *reinterpret_cast<const uint4 *>(&s_idx[l0 + 4 * h]);
+            const uint4 f = *reinterpret_cast<const uint4 *>(&s_first[l0 + 4 * h]);
+            idx[4 * h] = a.x; idx[4 * h + 1] = a.y; idx[4 * h + 2] = a.z; idx[4 * h + 3] = a.w;
+            fs[4 * h] = f.x; fs[4 * h + 1] = f.y; fs[4 * h + 2] = f.z; fs[4 * h + 3] = f.w;
+        }
+        uint32_t c = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) c += idx[i] < d.n0;
         uint32_t tot;
-        uint32_t j = base + dev::block_exclusive_sum(c, s_tmp, &tot);
+        uint32_t jl = dev::block_exclusive_sum(c, s_tmp, &tot);
 #pragma unroll
         for (int i = 0; i < kScanItems; ++i) {
             if (idx[i] < d.n0) {
-                if (j < d.n0) {
-                    keys0[j] = (uint32_t)first[r0 + i];
-                    vals0[j] = 3u * idx[i];
-                }
-                ++j;
+                s_k[jl] = fs[i];
+                s_v[jl] = 3u * idx[i];
+                ++jl;
+            }
+        }
+        __syncthreads();
+        for (uint32_t x = threadIdx.x; x < tot; x += kBlock) {
+            const uint32_t j = base + x;
+            if (j < d.n0) {
+                keys0[j] = s_k[x];
+                vals0[j] = s_v[x];
             }
         }
         base += tot;
+        __syncthreads();   // the next tile reuses the LDS
     }
 }
 
@@ -587,24 +745,56 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     const uint32_t g_el = grid_for(d.m);
     uint32_t hmax = 0;
 
-    const bool use_table = run && kb <= 24 && ((uint64_t)1 << kb) <= 2ull * d.m + 65536ull;
+    // Byte and int32 texts name through mixed-radix codes (A^3 of them) with
+    // word-window reads when the text is aligned for them; the pair-tagged
+    // texts of the batched path keep their b-bit packed keys.
+    const uint64_t A = (uint64_t)alphabet + 1;
+    const bool windowed = sizeof(CH) != 2 && A <= 1625 &&   // A^3 < 2^32
+                          ((uintptr_t)t % (sizeof(CH) == 1 ? 4 : 16)) == 0;
+    const uint64_t code_space = windowed ? A * A * A : (kb <= 24 ? (1ull << kb) : ~0ull);
+    const bool use_table = run && code_space <= (1ull << 24) && code_space <= 2ull * d.m + 65536ull;
     if (use_table) {
-        const uint32_t words = max(1u, (uint32_t)(((uint64_t)1 << kb) / 32));
+        const uint32_t words = max(1u, (uint32_t)div_up(code_space, 32));
         uint32_t *bitmap, *below, *stmp;
         LOR_TAKE(ar, uint32_t, words, bitmap);
         LOR_TAKE(ar, uint32_t, words, below);
         LOR_TAKE(ar, uint32_t, kScanTmpWords, stmp);
         LOR_TRY(zero_words(bitmap, words, s));
-        const int in_lds = words <= 8192;
-        LOR_LAUNCH("k_presence", (double)n * sizeof(CH), s,
-                   hipLaunchKernelGGL(k_presence<CH>, dim3(in_lds ? min(grid_for(d.m), 2048u) : grid_for(d.m)),
-                                      dim3(kBlock), in_lds ? words * 4 : 0, s, t, d, b, bitmap, words, in_lds));
-        LOR_LAUNCH("k_popc", 8.0 * words, s,
-                   hipLaunchKernelGGL(k_popc, dim3(grid_for(words)), dim3(kBlock), 0, s, bitmap, words, below));
-        LOR_TRY(scan_exclusive(below, words, stmp, hdr + 1, s));
-        LOR_LAUNCH("k_name_table", (double)n * sizeof(CH) + 4.0 * d.m, s,
-                   hipLaunchKernelGGL(k_name_table<CH>, dim3(g_el), dim3(kBlock), 0, s, t, d, b, bitmap, below, words,
-                                      R));
+        if constexpr (sizeof(CH) != 2) if (windowed) {
+            const size_t lds_max = max_lds_per_block();
+            const size_t pres_lds = (size_t)words * 4, name_lds = 4 * ((size_t)words + div_up(words, 4));
+            const int pres_in = pres_lds <= lds_max, name_in = name_lds <= lds_max;
+            const uint32_t groups = div_up(d.n0, kWinQ);
+            const uint32_t full = max(1u, div_up(groups, (uint32_t)kTblBlock));
+            const uint32_t gp = pres_in ? min(full, pres_lds <= 32768 ? 1024u : 256u) : full;
+            const uint32_t gn = name_in ? min(full, name_lds <= 32768 ? 1024u : 256u) : full;
+            if (pres_in)
+                LOR_LAUNCH("k_presence", (double)n * sizeof(CH), s,
+                           hipLaunchKernelGGL((k_presence_w<CH, true>), dim3(gp), dim3(kTblBlock), pres_lds, s, t, d,
+                                              (uint32_t)A, bitmap, words));
+            else
+                LOR_LAUNCH("k_presence", (double)n * sizeof(CH), s,
+                           hipLaunchKernelGGL((k_presence_w<CH, false>), dim3(gp), dim3(kTblBlock), 0, s, t, d,
+                                              (uint32_t)A, bitmap, words));
+            LOR_LAUNCH("k_popc", 8.0 * words, s,
+                       hipLaunchKernelGGL(k_popc, dim3(grid_for(words)), dim3(kBlock), 0, s, bitmap, words, below));
+            LOR_TRY(scan_exclusive(below, words, stmp, hdr + 1, s));
+            LOR_LAUNCH("k_name_table", (double)n * sizeof(CH) + 4.0 * d.m, s,
+                       hipLaunchKernelGGL(k_name_table_w<CH>, dim3(gn), dim3(kTblBlock), name_in ? name_lds : 0, s,
+                                          t, d, (uint32_t)A, bitmap, below, words, name_in, R));
+        }
+        if (!windowed) {
+            const int in_lds = words <= 8192;
+            LOR_LAUNCH("k_presence", (double)n * sizeof(CH), s,
+                       hipLaunchKernelGGL(k_presence<CH>, dim3(in_lds ? min(grid_for(d.m), 2048u) : grid_for(d.m)),
+                                          dim3(kBlock), in_lds ? words * 4 : 0, s, t, d, b, bitmap, words, in_lds));
+            LOR_LAUNCH("k_popc", 8.0 * words, s,
+                       hipLaunchKernelGGL(k_popc, dim3(grid_for(words)), dim3(kBlock), 0, s, bitmap, words, below));
+            LOR_TRY(scan_exclusive(below, words, stmp, hdr + 1, s));
+            LOR_LAUNCH("k_name_table", (double)n * sizeof(CH) + 4.0 * d.m, s,
+                       hipLaunchKernelGGL(k_name_table<CH>, dim3(g_el), dim3(kBlock), 0, s, t, d, b, bitmap, below,
+                                          words, R));
+        }
     } else if (km != KM_U32) {
         // 64-bit keys: whole triples, or (for wide symbols) two stages.
         uint64_t *k0, *k1;

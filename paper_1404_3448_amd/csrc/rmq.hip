@@ -8,9 +8,11 @@
 // cover its range. Levels 1-10 are built in one pass: a workgroup loads a
 // tile of the LCP array plus the halo the ten levels reach into, and
 // computes and writes those levels from LDS, so the LCP array is read once
-// for ten levels. Higher levels (windows wider than a tile) are built one at a
-// time from level k-1 (two streaming reads, one write per entry; tiles are
-// ordered so that most entries are fetched from HBM once). With 288 GB of HBM the table fits next to
+// for ten levels. Higher levels (windows wider than a tile) are built three
+// (or two) at a time from level k-1 by workgroups that walk columns of
+// blocks 2^(k-1) entries apart and keep the blocks they still need in
+// registers, so level k-1 is read about once per pass and every level is
+// written once. With 288 GB of HBM the table fits next to
 // the 1G-suffix arrays, and every query costs four independent gathers
 // (two ISA entries, two table entries) instead of a pointer walk.
 #include <climits>
@@ -57,12 +59,66 @@ __global__ __launch_bounds__(kBlock) void k_st_level(const int32_t *__restrict__
     }
 }
 
+__device__ __forceinline__ uint64_t level_offset_dev(uint64_t n, int level);
+
+// NL levels k .. k+NL-1 from level k-1 (P) in one pass. With h = 2^(k-1)
+// and blocks of B = 256 ITEMS entries (B divides h, H = h / B), output entry
+// i of level k+a is the minimum of P[i + u h] over u < 2^(a+1), and
+// i + u h lies u blocks of H further along the column of blocks
+// b, b + H, b + 2H, ... A workgroup walks `steps` consecutive blocks of one
+// column and keeps the last 2^NL blocks of P in registers, so each block of
+// P is read from HBM about once for all NL levels (instead of twice per
+// level); the writes are the table itself.
+template <int NL, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_st_chain(const int32_t *__restrict__ P, uint32_t cnt_p, uint32_t n,
+                                                     int k, uint32_t H, uint32_t nb, uint32_t steps,
+                                                     int32_t *__restrict__ table) {
+    constexpr int W = 1 << NL;
+    constexpr uint32_t B = kBlock * ITEMS;
+    const uint32_t c = blockIdx.x % H;
+    const uint32_t j0 = (blockIdx.x / H) * steps;
+    const uint32_t len = nb > c ? (nb - 1 - c) / H + 1 : 0;   // blocks of this column
+    if (j0 >= len) return;
+    const uint32_t j1 = min(len, j0 + steps);
+    int32_t win[W][ITEMS];
+    auto load = [&](uint32_t j, int32_t (&dst)[ITEMS]) {
+        const uint64_t base = (uint64_t)(c + (uint64_t)j * H) * B + threadIdx.x;
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const uint64_t idx = base + (uint64_t)r * kBlock;
+            dst[r] = idx < cnt_p ? P[idx] : INT_MAX;
+        }
+    };
+#pragma unroll
+    for (int u = 0; u < W - 1; ++u) load(j0 + u, win[u]);
+    for (uint32_t j = j0; j < j1; ++j) {
+        load(j + W - 1, win[W - 1]);
+        const uint64_t i0 = (uint64_t)(c + (uint64_t)j * H) * B + threadIdx.x;
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const uint64_t i = i0 + (uint64_t)r * kBlock;
+            int32_t m = win[0][r];
+#pragma unroll
+            for (int a = 0; a < NL; ++a) {
+#pragma unroll
+                for (int u = 1 << a; u < (2 << a); ++u) m = min(m, win[u][r]);
+                const int lv = k + a;
+                if (i < (uint64_t)n - (1ull << lv) + 1) table[level_offset_dev(n, lv) + i] = m;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < W - 1; ++u)
+#pragma unroll
+            for (int r = 0; r < ITEMS; ++r) win[u][r] = win[u + 1][r];
+    }
+}
+
+constexpr uint32_t kChainSteps = 64;        // blocks per workgroup along a column
+
 constexpr uint32_t kStTile = kBlock * 16;   // outputs per workgroup in fused levels
 constexpr int kStFuse = 10;                 // levels per fused pass
 constexpr int kStFusedTop = 10;             // levels 1..10 are built in LDS (halo < 1024 entries)
 constexpr uint32_t kRmqBlock = 64;          // LCP entries per block of the compact table
-
-__device__ __forceinline__ uint64_t level_offset_dev(uint64_t n, int level);
 
 // Levels k0 .. k0+nl-1 from level k0-1 (`prev`, prev_count entries) for the
 // outputs [i0, i0 + kStTile) of this workgroup.
@@ -316,15 +372,42 @@ lor_status rmq_build_levels(const int32_t *lcp, uint32_t n, int32_t *table, int 
                                       prev_count, n, k, nl, table));
         k += nl;
     }
-    for (; k <= levels; ++k) {
+    while (k <= levels) {
         const int32_t *prev = table + rmq_level_offset(n, k - 1);
-        int32_t *cur = table + rmq_level_offset(n, k);
         const uint32_t half = 1u << (k - 1);
-        const uint32_t cnt = n - (1u << k) + 1u;
-        const uint32_t tiles = div_up(cnt, kLvTile);
-        LOR_LAUNCH("k_st_level", (double)cnt * 8, s,
-                   hipLaunchKernelGGL(k_st_level, dim3(kXcds * div_up(tiles, kXcds)), dim3(kBlock), 0, s, prev, half,
-                                      cnt, tiles, cur));
+        const int nl = min(3, levels - k + 1);
+        const uint32_t items = half >= kBlock * 16u && nl < 3 ? 16u : (half >= kBlock * 8u ? 8u : 4u);
+        if (nl == 1 || half < kBlock * 4u) {
+            int32_t *cur = table + rmq_level_offset(n, k);
+            const uint32_t cnt = n - (1u << k) + 1u;
+            const uint32_t tiles = div_up(cnt, kLvTile);
+            LOR_LAUNCH("k_st_level", (double)cnt * 8, s,
+                       hipLaunchKernelGGL(k_st_level, dim3(kXcds * div_up(tiles, kXcds)), dim3(kBlock), 0, s, prev,
+                                          half, cnt, tiles, cur));
+            ++k;
+            continue;
+        }
+        const uint32_t B = kBlock * items, H = half / B;
+        const uint32_t cnt_p = n - half + 1u;
+        const uint32_t nb = div_up(n - (1u << k) + 1u, B);   // blocks holding level-k outputs
+        const uint32_t segs = div_up(div_up(nb, H), kChainSteps);
+        double bytes = 4.0 * cnt_p;
+        for (int a = 0; a < nl; ++a) bytes += 4.0 * (n - (1u << (k + a)) + 1u);
+        const dim3 grid(H * segs);
+#define LOR_CHAIN(NL, IT)                                                                                   \
+    LOR_LAUNCH("k_st_chain", bytes, s,                                                                      \
+               hipLaunchKernelGGL((k_st_chain<NL, IT>), grid, dim3(kBlock), 0, s, prev, cnt_p, n, k, H, nb, \
+                                  kChainSteps, table))
+        if (nl == 3) {
+            if (items == 4) LOR_CHAIN(3, 4);
+            else LOR_CHAIN(3, 8);
+        } else {
+            if (items == 4) LOR_CHAIN(2, 4);
+            else if (items == 8) LOR_CHAIN(2, 8);
+            else LOR_CHAIN(2, 16);
+        }
+#undef LOR_CHAIN
+        k += nl;
     }
     return LOR_OK;
 }
