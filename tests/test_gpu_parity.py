@@ -136,6 +136,24 @@ def test_dc3_periodic_texts(period, n):
     assert np.array_equal(sa_i32(t, 4), oracle.suffix_array(t))
 
 
+@pytest.mark.parametrize("offset", [0, 1, 2, 3])
+@pytest.mark.parametrize("alphabet", [4, 40])
+def test_dc3_text_at_any_alignment(offset, alphabet):
+    """A text that starts 4, 8 or 12 bytes past a 16-byte boundary takes the
+    per-symbol naming path (the word-window path needs 16-byte alignment);
+    both must give the oracle's order."""
+    n = 50_000
+    say("dc3 offset", offset, alphabet)
+    rng = np.random.default_rng(77 + offset + alphabet)
+    t = rng.integers(1, alphabet + 1, size=n).astype(np.int32)
+    buf = torch.zeros(n + 8, dtype=torch.int32, device="cuda")
+    view = buf[offset:offset + n]
+    view.copy_(torch.from_numpy(t))
+    assert view.data_ptr() % 16 == 4 * offset
+    got = host(lor.lor_suffix_array_i32(view, alphabet))
+    assert np.array_equal(got, oracle.suffix_array(t))
+
+
 # ----------------------------------------------------------- joined text
 
 def build(seqs):
