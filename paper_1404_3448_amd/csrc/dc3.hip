@@ -152,16 +152,20 @@ __global__ __launch_bounds__(kBlock) void k_join(const uint8_t *__restrict__ seq
 
 // ------------------------------------------------------- Step 1: keys
 
-// mode 0: packed triple key (t_i, t_{i+1}, t_{i+2});
+// mode 0: triple key (t_i, t_{i+1}, t_{i+2}), b-bit fields or mixed radix
+// mixA (nonzero);
 // mode 1: packed pair (t_{i+1}, t_{i+2}) of b-bit symbols, the first stage of
 // wide triples.
 template <typename CH, typename K>
 __global__ __launch_bounds__(kBlock) void k_sample_keys(const CH *__restrict__ t, Dims d, int b, int mode,
-                                                        K *__restrict__ keys, uint32_t *__restrict__ vals) {
+                                                        uint64_t mixA, K *__restrict__ keys,
+                                                        uint32_t *__restrict__ vals) {
     for (uint32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < d.m; idx += gridDim.x * kBlock) {
         const uint32_t p = d.pos_of(idx);
         K key;
-        if (mode == 0) {
+        if (mode == 0 && mixA) {   // mixed radix; A^3 fits K
+            key = ((K)sym(t, d.n, p) * (K)mixA + (K)sym(t, d.n, p + 1)) * (K)mixA + (K)sym(t, d.n, p + 2);
+        } else if (mode == 0) {
             key = Triple<CH>::template pack<K>(t, d, b, p);
         } else {
             key = ((K)sym(t, d.n, p + 1) << b) | (K)sym(t, d.n, p + 2);
@@ -731,7 +735,21 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
 
     // ---- Step 1: sort the sample triples
     const int kb = Triple<CH>::key_bits(b);
-    KeyMode km = (kb <= 32) ? KM_U32 : (kb <= 64 ? KM_U64 : KM_STAGED);
+    // Sort keys of byte and int32 texts are mixed-radix, (s0 A + s1) A + s2
+    // with A = alphabet + 1, when that takes fewer bits than three b-bit
+    // fields (level 2 of the 1G text: 54 bits instead of 57, one radix pass
+    // fewer).
+    const uint64_t mixA = (uint64_t)alphabet + 1;
+    int kbs = kb;
+    bool mixed = false;
+    if (sizeof(CH) != 2 && mixA <= (1ull << 21)) {   // A^3 < 2^63
+        const int mb = bits_for(mixA * mixA * mixA - 1);
+        if (mb < kb) {
+            kbs = mb;
+            mixed = true;
+        }
+    }
+    KeyMode km = (kbs <= 32) ? KM_U32 : (kbs <= 64 ? KM_U64 : KM_STAGED);
     if (!run) km = KM_U64;   // measuring: the largest footprint
     uint32_t *counts;
     LOR_TAKE(ar, uint32_t, radix_counts_words(d.m) + kMaxScanGroups + 64, counts);
@@ -739,7 +757,7 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     uint32_t *tmpv;
     LOR_TAKE(ar, uint32_t, d.m, tmpv);
     const int passes = d.m <= 1 ? 0
-                       : (km == KM_STAGED ? radix_passes(0, 2 * b) + radix_passes(32, 32 + b) : radix_passes(0, kb));
+                       : (km == KM_STAGED ? radix_passes(0, 2 * b) + radix_passes(32, 32 + b) : radix_passes(0, kbs));
     uint32_t *v0 = (passes % 2 == 0) ? (uint32_t *)sa12 : tmpv;
     uint32_t *v1 = (passes % 2 == 0) ? tmpv : (uint32_t *)sa12;
     const uint32_t g_el = grid_for(d.m);
@@ -821,14 +839,14 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
             if (km == KM_U64) {
                 LOR_LAUNCH("k_sample_keys", (double)d.m * 12 + (double)n * sizeof(CH), s,
                            hipLaunchKernelGGL((k_sample_keys<CH, uint64_t>), dim3(g_el), dim3(kBlock), 0, s, t, d, b,
-                                              0, kc, vc));
-                LOR_TRY(radix_sort<uint64_t>(kc, vc, ka, va, d.m, 0, kb, counts, s, &alt));
+                                              0, mixed ? mixA : 0ull, kc, vc));
+                LOR_TRY(radix_sort<uint64_t>(kc, vc, ka, va, d.m, 0, kbs, counts, s, &alt));
                 swap_if(alt);
             } else {
                 // stage A: sort the pairs (t_{i+1}, t_{i+2}) and rank them
                 LOR_LAUNCH("k_sample_keys", (double)d.m * 12 + (double)n * sizeof(CH), s,
                            hipLaunchKernelGGL((k_sample_keys<CH, uint64_t>), dim3(g_el), dim3(kBlock), 0, s, t, d, b,
-                                              1, kc, vc));
+                                              1, 0ull, kc, vc));
                 LOR_TRY(radix_sort<uint64_t>(kc, vc, ka, va, d.m, 0, 2 * b, counts, s, &alt));
                 swap_if(alt);
                 LOR_LAUNCH("k_name_count", (double)d.m * 8, s,
@@ -872,8 +890,8 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
             uint32_t *kc = k0, *ka = k1, *vc = v0, *va = v1;
             LOR_LAUNCH("k_sample_keys", (double)d.m * 8 + (double)n * sizeof(CH), s,
                        hipLaunchKernelGGL((k_sample_keys<CH, uint32_t>), dim3(g_el), dim3(kBlock), 0, s, t, d, b, 0,
-                                          kc, vc));
-            LOR_TRY(radix_sort<uint32_t>(kc, vc, ka, va, d.m, 0, kb, counts, s, &alt));
+                                          mixed ? mixA : 0ull, kc, vc));
+            LOR_TRY(radix_sort<uint32_t>(kc, vc, ka, va, d.m, 0, kbs, counts, s, &alt));
             if (alt) {
                 uint32_t *x = kc; kc = ka; ka = x;
                 x = vc; vc = va; va = x;

@@ -111,8 +111,10 @@ __global__ __launch_bounds__(kBlock) void k_init(uint32_t *w, int count) {
 
 // Largest LCP[r] whose two suffixes start in different sequences. A
 // workgroup takes kCrossItems * 256 consecutive ranks; each thread loads its
-// LCP and SA entries (and the SA entry one rank below) for all its items
-// before comparing, so the loads overlap.
+// LCP entries for all its items first. SA entries are loaded only for ranks
+// whose LCP exceeds both the maximum already published by earlier
+// workgroups (a lower bound of the result) and the thread's own best, so
+// after the first workgroups almost every rank costs its 4-byte LCP alone.
 constexpr int kCrossItems = 16;
 
 __global__ __launch_bounds__(kBlock) void k_cross_max(const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp,
@@ -120,28 +122,30 @@ __global__ __launch_bounds__(kBlock) void k_cross_max(const int32_t *__restrict_
     __shared__ int32_t s_start[kMaxSeqs + 1];
     __shared__ int32_t s_red[kBlock / kWave];
     for (int i = threadIdx.x; i <= st.k; i += kBlock) s_start[i] = st.start[i];
+    const int32_t known = (int32_t)__hip_atomic_load(out_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const uint32_t r0 = blockIdx.x * (kBlock * kCrossItems) + threadIdx.x + 1;
-    int32_t v[kCrossItems], a[kCrossItems], b[kCrossItems];
+    int32_t v[kCrossItems];
 #pragma unroll
     for (int j = 0; j < kCrossItems; ++j) {
         const uint32_t r = r0 + j * kBlock;
-        const bool ok = r < n;
-        v[j] = ok ? lcp[r] : 0;
-        a[j] = ok ? sa[r - 1] : 0;
-        b[j] = ok ? sa[r] : 0;
+        v[j] = r < n ? lcp[r] : 0;
     }
     int32_t best = 0;
 #pragma unroll
-    for (int j = 0; j < kCrossItems; ++j)
-        if (v[j] > best && seq_of(s_start, st.k, a[j]) != seq_of(s_start, st.k, b[j])) best = v[j];
+    for (int j = 0; j < kCrossItems; ++j) {
+        const uint32_t r = r0 + j * kBlock;
+        if (v[j] > known && v[j] > best &&
+            seq_of(s_start, st.k, sa[r - 1]) != seq_of(s_start, st.k, sa[r]))   // v[j] > 0 implies r < n
+            best = v[j];
+    }
     for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o, 64));
     if ((threadIdx.x & 63u) == 0) s_red[threadIdx.x >> 6] = best;
     __syncthreads();
     if (threadIdx.x == 0) {
         int32_t m = s_red[0];
         for (int i = 1; i < kBlock / kWave; ++i) m = max(m, s_red[i]);
-        if (m > 0) atomicMax(out_max, (uint32_t)m);
+        if (m > known) atomicMax(out_max, (uint32_t)m);
     }
 }
 
@@ -154,17 +158,22 @@ __device__ void block_reduce_chunks(ChunkSum *s, ChunkSum mine) {
     }
 }
 
+// One workgroup per group of kTilesPerGroup tiles. First every tile is
+// checked for an LCP >= L with all its loads in flight at once; tiles
+// without one (nearly all) hold only one-suffix runs and are summarised by
+// one thread each from their last suffix, the others go through the
+// per-rank path. The tile summaries are then combined in rank order.
 __global__ __launch_bounds__(kBlock) void k_runs(const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp,
                                                  uint32_t n, SeqStarts st, const uint32_t *__restrict__ Lp,
                                                  ChunkSum *__restrict__ out) {
     __shared__ int32_t s_start[kMaxSeqs + 1];
     __shared__ ChunkSum s_sum[kBlock];
-    __shared__ int32_t s_sa[kTileRanks];
-    __shared__ int32_t s_lcp[kTileRanks];
+    __shared__ ChunkSum s_tile[kTilesPerGroup];
+    __shared__ uint32_t s_any[kTilesPerGroup];
     for (int i = threadIdx.x; i <= st.k; i += kBlock) s_start[i] = st.start[i];
+    if (threadIdx.x < kTilesPerGroup) s_any[threadIdx.x] = 0;
     __syncthreads();
     const int32_t L = (int32_t)*Lp;
-    ChunkSum total = chunk_empty();                 // meaningful in thread 0
     const uint32_t tiles = (n + kTileRanks - 1) / kTileRanks;
     const uint32_t t0 = blockIdx.x * kTilesPerGroup, t1 = min(tiles, t0 + kTilesPerGroup);
     for (uint32_t t = t0; t < t1; ++t) {
@@ -174,35 +183,32 @@ __global__ __launch_bounds__(kBlock) void k_runs(const int32_t *__restrict__ sa,
 #pragma unroll
         for (uint32_t i = 0; i < kChunk; ++i) {
             const uint32_t j = i * kBlock + threadIdx.x;
-            const int32_t v = j < cnt ? lcp[base + j] : 0;
-            if (j < cnt) s_lcp[j] = v;
-            any |= (base + j != 0) && j < cnt && v >= L;
+            any |= j < cnt && (base + j != 0) && lcp[base + j] >= L;
         }
-        any = __syncthreads_or(any);
-        if (!any) {
-            // every rank starts a run; only the last run can continue
-            if (threadIdx.x == 0) {
-                const int32_t p = sa[base + cnt - 1];
-                ChunkSum c = chunk_empty();
-                c.has_b = 1;
-                c.tail = RunSum{p, seq_of(s_start, st.k, p), INT_MAX, -1};
-                total = chunk_combine(total, c);
-            }
-            __syncthreads();
-            continue;
-        }
-#pragma unroll
-        for (uint32_t i = 0; i < kChunk; ++i) {
-            const uint32_t j = i * kBlock + threadIdx.x;
-            if (j < cnt) s_sa[j] = sa[base + j];
-        }
-        __syncthreads();
+        if (__any(any) && (threadIdx.x & 63u) == 0) s_any[t - t0] = 1;   // LDS store; any wave may set it
+    }
+    __syncthreads();
+    if (threadIdx.x < t1 - t0 && !s_any[threadIdx.x]) {
+        // every rank starts a run; only the last run can continue
+        const uint32_t base = (t0 + threadIdx.x) * kTileRanks;
+        const uint32_t cnt = min(kTileRanks, n - base);
+        const int32_t p = sa[base + cnt - 1];
+        ChunkSum c = chunk_empty();
+        c.has_b = 1;
+        c.tail = RunSum{p, seq_of(s_start, st.k, p), INT_MAX, -1};
+        s_tile[threadIdx.x] = c;
+    }
+    for (uint32_t t = t0; t < t1; ++t) {
+        if (!s_any[t - t0]) continue;   // uniform: s_any is final after the barrier above
+        // rare (tiles inside a longest run): each thread reads its ranks directly
+        const uint32_t base = t * kTileRanks;
+        const uint32_t cnt = min(kTileRanks, n - base);
         ChunkSum c = chunk_empty();
         const uint32_t j0 = threadIdx.x * kChunk;
         for (uint32_t j = j0; j < min(cnt, j0 + kChunk); ++j) {
-            const int32_t p = s_sa[j];
+            const int32_t p = sa[base + j];
             const RunSum e{p, seq_of(s_start, st.k, p), INT_MAX, -1};
-            if (base + j == 0 || s_lcp[j] < L) {    // starts a run
+            if (base + j == 0 || lcp[base + j] < L) {    // starts a run
                 if (c.has_b) finalize(c.tail, c.bp, c.bq);
                 c.has_b = 1;
                 c.tail = e;
@@ -213,10 +219,15 @@ __global__ __launch_bounds__(kBlock) void k_runs(const int32_t *__restrict__ sa,
             }
         }
         block_reduce_chunks(s_sum, c);
-        if (threadIdx.x == 0) total = chunk_combine(total, s_sum[0]);
+        if (threadIdx.x == 0) s_tile[t - t0] = s_sum[0];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[blockIdx.x] = total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ChunkSum total = chunk_empty();
+        for (uint32_t t = t0; t < t1; ++t) total = chunk_combine(total, s_tile[t - t0]);
+        out[blockIdx.x] = total;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_runs_final(const ChunkSum *__restrict__ in, uint32_t count,
@@ -253,7 +264,7 @@ lor_status overlap_scan(const int32_t *sa, const int32_t *lcp, uint32_t n, const
     result[0] = 0;
     if (n < 2) return LOR_OK;
     LOR_LAUNCH("k_init", 0, s, hipLaunchKernelGGL(k_init, dim3(1), dim3(kBlock), 0, s, words, 4));
-    LOR_LAUNCH("k_cross_max", (double)n * 8, s,
+    LOR_LAUNCH("k_cross_max", (double)n * 4, s,   // LCP; SA only for the few ranks above the running maximum
                hipLaunchKernelGGL(k_cross_max, dim3(div_up(n - 1, kBlock * kCrossItems)), dim3(kBlock), 0, s, sa, lcp,
                                   n, st, words));
     uint32_t L = 0;
