@@ -392,6 +392,10 @@ def main():
         gbs = k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0
         kern_out[name] = {"launches_per_step": k["launches"] / args.steps, "ms_per_step": round(k["ms"] / args.steps, 3),
                           "alg_GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+        # HBM bytes the counters measured for this kernel (1G workload, same sources) over the same time
+        per_launch = committed_traffic(name) if args.workload == "1g" and k["ms"] > 0 else None
+        if per_launch is not None:
+            kern_out[name]["hbm_GBps"] = round(per_launch * k["launches"] / (k["ms"] * 1e-3) / 1e9, 1)
     if kernels:
         dom_name, dom = max(kernels.items(), key=lambda kv: kv[1]["ms"])
         achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
