@@ -150,11 +150,16 @@ __global__ __launch_bounds__(kBlock, 2) void k_radix_scatter(const K *__restrict
     constexpr uint32_t TILE = kBlock * ITEMS;
     constexpr int W = kBlock / kWave;
     __shared__ uint32_t s_cnt[W][kBins];     // per-wave digit counters, then per-wave digit bases
-    __shared__ uint64_t s_match[W][kBins];   // per-wave lane masks of one item's digit
     __shared__ uint32_t s_delta[kBins];      // global index minus tile slot, per digit
     __shared__ uint32_t s_tmp[W];
-    __shared__ K s_key[TILE];
-    __shared__ uint32_t s_val[TILE];
+    // The per-wave lane masks of one item's digit are dead once the ranks are
+    // known, before the tile is reordered: they share LDS with the tile.
+    constexpr size_t kMatchBytes = sizeof(uint64_t) * W * kBins;
+    constexpr size_t kTileBytes = (sizeof(K) + sizeof(uint32_t)) * TILE;
+    __shared__ __align__(16) unsigned char s_raw[kMatchBytes > kTileBytes ? kMatchBytes : kTileBytes];
+    uint64_t(*s_match)[kBins] = reinterpret_cast<uint64_t(*)[kBins]>(s_raw);
+    K *s_key = reinterpret_cast<K *>(s_raw);
+    uint32_t *s_val = reinterpret_cast<uint32_t *>(s_raw + sizeof(K) * TILE);
 
     uint32_t t;
     if (!xcd_tile(tiles, &t)) return;
@@ -182,18 +187,19 @@ __global__ __launch_bounds__(kBlock, 2) void k_radix_scatter(const K *__restrict
     __syncthreads();
 
     // Peer masks of every item: OR, read back, clear (no waits in between).
-    // dg[r] holds the item's digit, or kBins for a slot past the end.
-    uint32_t dg[ITEMS];
+    // dr[r] holds the item's digit (kBins for a slot past the end) in its low
+    // 9 bits and, once known, its rank among the wave's items of that digit
+    // above them (digit and rank share a register).
+    uint32_t dr[ITEMS];
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r)
-        dg[r] = (first + r * kWave < n) ? ((uint32_t)(k[r] >> shift) & mask) : (uint32_t)kBins;
+        dr[r] = (first + r * kWave < n) ? ((uint32_t)(k[r] >> shift) & mask) : (uint32_t)kBins;
     uint32_t *mw = reinterpret_cast<uint32_t *>(&s_match[w][0]);
     const uint32_t lbit = 1u << (lane & 31u), half = lane >> 5;
     // Items go in chunks: the mask operations of a whole chunk are issued
     // back to back, then its count operations, so LDS latency is paid once
     // per chunk and few masks are live at a time.
     constexpr int CH = (ITEMS % 8 == 0) ? 8 : 4;
-    uint32_t rk[ITEMS];
 #pragma unroll
     for (int c0 = 0; c0 < ITEMS; c0 += CH) {
         uint64_t pm[CH];
@@ -201,8 +207,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_radix_scatter(const K *__restrict
         for (int j = 0; j < CH; ++j) {
             const int r = c0 + j;
             pm[j] = 0;
-            if (dg[r] < kBins) {
-                uint32_t *word = &mw[2 * dg[r]];
+            if (dr[r] < kBins) {
+                uint32_t *word = &mw[2 * dr[r]];
                 __hip_atomic_fetch_or(word + half, lbit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 pm[j] = __hip_atomic_load(reinterpret_cast<uint64_t *>(word), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -217,14 +223,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_radix_scatter(const K *__restrict
             const int r = c0 + j;
             const uint32_t below = dev::count_below(pm[j]);
             uint32_t old = 0;
-            if (dg[r] < kBins) {
-                uint32_t *cnt = &s_cnt[w][dg[r]];
+            if (dr[r] < kBins) {
+                uint32_t *cnt = &s_cnt[w][dr[r]];
                 old = __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (below == 0)
                     __hip_atomic_fetch_add(cnt, (uint32_t)__popcll(pm[j]), __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-            rk[r] = old + below;
+            dr[r] |= (old + below) << 9;
         }
     }
     __syncthreads();
@@ -248,8 +254,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_radix_scatter(const K *__restrict
 
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-        const uint32_t lp = s_cnt[w][min(dg[r], (uint32_t)kBins - 1u)] + rk[r];
-        if (dg[r] < kBins && lp < TILE) {   // always true for a consistent ranking
+        const uint32_t d = dr[r] & 511u;
+        const uint32_t lp = s_cnt[w][min(d, (uint32_t)kBins - 1u)] + (dr[r] >> 9);
+        if (d < kBins && lp < TILE) {   // always true for a consistent ranking
             s_key[lp] = k[r];
             s_val[lp] = v[r];
         }
