@@ -619,12 +619,10 @@ __global__ __launch_bounds__(kBlock) void k_ns_write(const int32_t *__restrict__
 
 // A = mod-0 positions sorted (Step 2), B = sample order without the padding
 // position (R-indices). Merge path: the number of A elements among the first
-// `diag` outputs, by binary search.
+// `diag` outputs, by binary search inside [lo, hi] (which must hold it).
 template <typename CH>
-__device__ __forceinline__ uint32_t merge_split(const Rec<CH> *rec, const uint32_t *A, uint32_t nA,
-                                                const int32_t *B, uint32_t nB, const Dims &d,
-                                                uint32_t diag) {
-    uint32_t lo = diag > nB ? diag - nB : 0u, hi = min(diag, nA);
+__device__ __forceinline__ uint32_t merge_split(const Rec<CH> *rec, const uint32_t *A, const int32_t *B,
+                                                const Dims &d, uint32_t diag, uint32_t lo, uint32_t hi) {
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
         const Key4 a = key_of<CH>(rec, min(A[mid], d.n - 1));
@@ -634,17 +632,31 @@ __device__ __forceinline__ uint32_t merge_split(const Rec<CH> *rec, const uint32
     return lo;
 }
 
+// Splits at diagonals p * tile for p = 0..parts. The split is monotone in the
+// diagonal, so a first launch over every kCoarse-th diagonal (coarse ==
+// nullptr) bounds the searches of the second launch to one coarse interval:
+// about 16 steps instead of about 30, and the coarse searches share the top
+// of every later search.
+constexpr uint32_t kCoarse = 64;
+
 template <typename CH>
 __global__ __launch_bounds__(kBlock) void k_merge_partition(const Rec<CH> *__restrict__ rec,
                                                             const uint32_t *__restrict__ A, uint32_t nA,
                                                             const int32_t *__restrict__ B, uint32_t nB,
-                                                            Dims d, uint32_t parts, uint32_t tile,
+                                                            Dims d, uint32_t parts, uint64_t tile,
+                                                            const uint32_t *__restrict__ coarse, uint32_t cparts,
                                                             uint32_t *__restrict__ split) {
     const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
     if (p > parts) return;
-    const uint64_t diag64 = (uint64_t)p * tile;
-    const uint32_t diag = (uint32_t)min<uint64_t>(diag64, (uint64_t)nA + nB);
-    split[p] = merge_split<CH>(rec, A, nA, B, nB, d, diag);
+    const uint32_t diag = (uint32_t)min<uint64_t>((uint64_t)p * tile, (uint64_t)nA + nB);
+    const uint32_t lo0 = diag > nB ? diag - nB : 0u, hi0 = min(diag, nA);
+    uint32_t lo = lo0, hi = hi0;
+    if (coarse) {
+        const uint32_t c = p / kCoarse;
+        lo = min(max(lo0, coarse[c]), hi0);
+        hi = max(min(hi0, coarse[min(c + 1, cparts)]), lo);
+    }
+    split[p] = merge_split<CH>(rec, A, B, d, diag, lo, hi);
 }
 
 template <typename CH, int ITEMS>
@@ -987,8 +999,9 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     const int mitems = plan().merge_items;
     const uint32_t mtile = kBlock * (uint32_t)mitems;
     const uint32_t parts = div_up(n, mtile);
-    uint32_t *split;   // sized for the smallest merge tile, so the workspace does not depend on the plan
+    uint32_t *split, *csplit;   // sized for the smallest merge tile, so the workspace does not depend on the plan
     LOR_TAKE(ar, uint32_t, (size_t)div_up(n, kBlock * 4) + 2, split);
+    LOR_TAKE(ar, uint32_t, (size_t)div_up(n, kBlock * 4 * kCoarse) + 2, csplit);
     if (run) {
         // first symbols of the mod-0 suffixes in sample order, into R (the
         // ranks are consumed by k_ns_pairs; the records already hold them)
@@ -1009,9 +1022,14 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
         const uint32_t *A = alt ? vals1 : vals0;
         const int32_t *B = sa12 + d.dummy;
         const uint32_t nB = d.m - d.dummy;
+        const uint32_t cparts = div_up(parts, kCoarse);
+        LOR_LAUNCH("k_merge_partition", (double)(cparts + 1) * 4, s,
+                   hipLaunchKernelGGL(k_merge_partition<CH>, dim3(div_up(cparts + 1, kBlock)), dim3(kBlock), 0, s,
+                                      rec, A, d.n0, B, nB, d, cparts, (uint64_t)mtile * kCoarse, nullptr, 0u,
+                                      csplit));
         LOR_LAUNCH("k_merge_partition", (double)(parts + 1) * 4, s,
                    hipLaunchKernelGGL(k_merge_partition<CH>, dim3(div_up(parts + 1, kBlock)), dim3(kBlock), 0, s,
-                                      rec, A, d.n0, B, nB, d, parts, mtile, split));
+                                      rec, A, d.n0, B, nB, d, parts, (uint64_t)mtile, csplit, cparts, split));
         const double mbytes = (double)n * (4 + 4 + sizeof(Rec<CH>));
         switch (mitems) {
             case 4:
