@@ -40,19 +40,70 @@ __device__ __forceinline__ uint32_t find_pair(const int32_t *__restrict__ start,
     return lo;
 }
 
+// Ranks (and positions) of one workgroup span few pairs. Pairs [lo, lo + k)
+// cover the workgroup's range [r0, r1]; with k <= kPairWin their starts (and
+// the start after the last) and |A| are kept in LDS, and each thread, whose
+// ranks only increase, finds its pair by advancing a cursor there. Larger k
+// (very short pairs) falls back to a binary search over all pairs.
+constexpr uint32_t kPairWin = 1024;
+
+struct PairWin {
+    uint32_t lo, k;
+    bool lds;
+};
+
+__device__ PairWin pair_window(const int32_t *__restrict__ start, const int32_t *__restrict__ alen, uint32_t P,
+                               uint32_t r0, uint32_t r1, int32_t *s_start, int32_t *s_alen, uint32_t *s_sh) {
+    if (threadIdx.x == 0) s_sh[0] = find_pair(start, P, r0);
+    if (threadIdx.x == 1) s_sh[1] = find_pair(start, P, r1);
+    __syncthreads();
+    PairWin w;
+    w.lo = s_sh[0];
+    w.k = s_sh[1] - s_sh[0] + 1;
+    w.lds = w.k <= kPairWin;
+    if (w.lds) {
+        for (uint32_t j = threadIdx.x; j <= w.k; j += kBlock) s_start[j] = start[w.lo + j];   // start[P] = N exists
+        for (uint32_t j = threadIdx.x; j < w.k; j += kBlock) s_alen[j] = alen[w.lo + j];
+    }
+    __syncthreads();
+    return w;
+}
+
+// Pair of x relative to w.lo; x must not decrease between the calls of one
+// thread that share `cur` (which starts at 0).
+__device__ __forceinline__ uint32_t pair_at(const PairWin &w, const int32_t *s_start, const int32_t *__restrict__ start,
+                                            uint32_t P, uint32_t x, uint32_t &cur) {
+    if (w.lds) {
+        while (cur + 1 < w.k && (uint32_t)s_start[cur + 1] <= x) ++cur;
+        return cur;
+    }
+    return find_pair(start, P, x) - w.lo;
+}
+
 // start[p] = joined start of pair p (start[P] = N); alen[p] = |A_p|;
 // src[2p], src[2p+1] = offsets of A_p and B_p in the separator-free input.
+constexpr uint32_t kJoinTile = kBlock * 16;   // positions per workgroup
+
 __global__ __launch_bounds__(kBlock) void k_join_pairs(const uint8_t *__restrict__ seqs,
                                                        const int32_t *__restrict__ start,
                                                        const int32_t *__restrict__ alen,
                                                        const int64_t *__restrict__ src, uint32_t P, uint32_t N,
                                                        uint16_t *__restrict__ out, uint32_t *__restrict__ err) {
-    uint32_t bad = 0;
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
-        const uint32_t p = find_pair(start, P, i);
-        const uint32_t o = i - (uint32_t)start[p];
-        const uint32_t a = (uint32_t)alen[p];
-        const uint32_t plen = (uint32_t)start[p + 1] - (uint32_t)start[p];
+    __shared__ int32_t s_start[kPairWin + 1];
+    __shared__ int32_t s_alen[kPairWin];
+    __shared__ uint32_t s_sh[2];
+    const uint32_t base = blockIdx.x * kJoinTile;
+    if (base >= N) return;
+    const uint32_t cnt = min(kJoinTile, N - base);
+    const PairWin w = pair_window(start, alen, P, base, base + cnt - 1, s_start, s_alen, s_sh);
+    uint32_t bad = 0, cur = 0;
+    for (uint32_t j = threadIdx.x; j < cnt; j += kBlock) {
+        const uint32_t i = base + j;
+        const uint32_t q = pair_at(w, s_start, start, P, i, cur), p = w.lo + q;
+        const uint32_t s0 = w.lds ? (uint32_t)s_start[q] : (uint32_t)start[p];
+        const uint32_t s1 = w.lds ? (uint32_t)s_start[q + 1] : (uint32_t)start[p + 1];
+        const uint32_t a = w.lds ? (uint32_t)s_alen[q] : (uint32_t)alen[p];
+        const uint32_t o = i - s0, plen = s1 - s0;
         uint32_t code;
         if (o < a) {
             code = seqs[src[2 * p] + o];
@@ -85,30 +136,55 @@ __device__ __forceinline__ bool in_b(const int32_t *start, const int32_t *alen, 
     return x > (uint32_t)start[p] + (uint32_t)alen[p];
 }
 
+// Per pair, the largest LCP between suffixes of its two sequences. A
+// workgroup takes one tile of ranks; SA is read only for ranks whose LCP
+// exceeds the maximum its pair already has (published by earlier
+// workgroups, a lower bound of the result), and maxima meet in LDS before
+// one atomicMax per pair and workgroup.
 __global__ __launch_bounds__(kBlock) void k_seg_max(const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp,
                                                     uint32_t n, const int32_t *__restrict__ start,
                                                     const int32_t *__restrict__ alen, uint32_t P,
                                                     uint32_t *__restrict__ lmax) {
-    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
-        const uint32_t r = base + threadIdx.x;
-        uint32_t p = 0, v = 0;
-        if (r < n) {
-            p = find_pair(start, P, r);
-            if (r > (uint32_t)start[p]) {
-                const int32_t l = lcp[r];
-                if (l > 0 && in_b(start, alen, p, (uint32_t)sa[r - 1]) != in_b(start, alen, p, (uint32_t)sa[r]))
-                    v = (uint32_t)l;
-            }
+    __shared__ int32_t s_start[kPairWin + 1];
+    __shared__ int32_t s_alen[kPairWin];
+    __shared__ uint32_t s_known[kPairWin];
+    __shared__ uint32_t s_best[kPairWin];
+    __shared__ uint32_t s_sh[2];
+    const uint32_t base = blockIdx.x * kTileRanks;
+    if (base >= n) return;
+    const uint32_t cnt = min(kTileRanks, n - base);
+    const PairWin w = pair_window(start, alen, P, base, base + cnt - 1, s_start, s_alen, s_sh);
+    if (w.lds) {
+        for (uint32_t j = threadIdx.x; j < w.k; j += kBlock) {
+            s_known[j] = __hip_atomic_load(&lmax[w.lo + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_best[j] = 0;
         }
-        // one atomic per wave when the wave lies inside one pair
-        const uint32_t p0 = __shfl(p, 0, 64);
-        if (__all(r >= n || p == p0)) {
-            uint32_t m = v;
-            for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
-            if (dev::lane_id() == 0 && m > 0) atomicMax(&lmax[p0], m);
-        } else if (v > 0) {
-            atomicMax(&lmax[p], v);
-        }
+        __syncthreads();
+    }
+    int32_t v[kChunk];
+#pragma unroll
+    for (uint32_t i = 0; i < kChunk; ++i) {
+        const uint32_t j = i * kBlock + threadIdx.x;
+        v[i] = j < cnt ? lcp[base + j] : 0;
+    }
+    uint32_t cur = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kChunk; ++i) {
+        const uint32_t j = i * kBlock + threadIdx.x;
+        if (j >= cnt || v[i] <= 0) continue;
+        const uint32_t r = base + j;
+        const uint32_t q = pair_at(w, s_start, start, P, r, cur), p = w.lo + q;
+        const uint32_t s0 = w.lds ? (uint32_t)s_start[q] : (uint32_t)start[p];
+        if (r <= s0 || (w.lds && (uint32_t)v[i] <= s_known[q])) continue;
+        const uint32_t bstart = s0 + (w.lds ? (uint32_t)s_alen[q] : (uint32_t)alen[p]);   // B starts after it
+        if (((uint32_t)sa[r - 1] > bstart) == ((uint32_t)sa[r] > bstart)) continue;
+        if (w.lds) atomicMax(&s_best[q], (uint32_t)v[i]);
+        else atomicMax(&lmax[p], (uint32_t)v[i]);
+    }
+    if (w.lds) {
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < w.k; j += kBlock)
+            if (s_best[j] > s_known[j]) atomicMax(&lmax[w.lo + j], s_best[j]);
     }
 }
 
@@ -169,15 +245,6 @@ __device__ __forceinline__ ChunkSum chunk_combine(const ChunkSum &x, const Chunk
     return r;
 }
 
-// Rank r starts a run unless it shares at least its pair's L symbols with r-1.
-__device__ __forceinline__ bool run_start(uint32_t r, int32_t l, const int32_t *start, uint32_t P,
-                                          const uint32_t *lmax, uint32_t *pair_out) {
-    const uint32_t p = find_pair(start, P, r);
-    *pair_out = p;
-    const uint32_t L = lmax[p];
-    return r == (uint32_t)start[p] || L == 0 || (uint32_t)l < L;
-}
-
 __device__ void reduce_chunks(ChunkSum *s, ChunkSum mine, const int32_t *start, uint32_t P,
                               unsigned long long *best) {
     s[threadIdx.x] = mine;
@@ -189,6 +256,12 @@ __device__ void reduce_chunks(ChunkSum *s, ChunkSum mine, const int32_t *start, 
     }
 }
 
+// One workgroup per group of kTilesPerGroup tiles. Rank r starts a run
+// unless it shares at least its pair's L symbols with r - 1. Every tile is
+// first checked for a rank that continues a run, with all its loads in
+// flight at once; tiles without one (nearly all) hold only one-suffix runs
+// and are summarised by one thread each from their last suffix, the others
+// go through the per-rank path. Tile summaries are combined in rank order.
 __global__ __launch_bounds__(kBlock) void k_seg_runs(const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp,
                                                      uint32_t n, const int32_t *__restrict__ start,
                                                      const int32_t *__restrict__ alen, uint32_t P,
@@ -196,52 +269,75 @@ __global__ __launch_bounds__(kBlock) void k_seg_runs(const int32_t *__restrict__
                                                      unsigned long long *__restrict__ best,
                                                      ChunkSum *__restrict__ out) {
     __shared__ ChunkSum s_sum[kBlock];
-    __shared__ int32_t s_sa[kTileRanks];
-    __shared__ int32_t s_lcp[kTileRanks];
-    ChunkSum total = chunk_empty();
+    __shared__ ChunkSum s_tile[kTilesPerGroup];
+    __shared__ uint32_t s_any[kTilesPerGroup];
+    __shared__ int32_t s_start[kPairWin + 1];
+    __shared__ int32_t s_alen[kPairWin];
+    __shared__ uint32_t s_L[kPairWin];
+    __shared__ uint32_t s_sh[2];
     const uint32_t tiles = (n + kTileRanks - 1) / kTileRanks;
     const uint32_t t0 = blockIdx.x * kTilesPerGroup, t1 = min(tiles, t0 + kTilesPerGroup);
+    if (t0 >= t1) return;
+    const uint32_t g0 = t0 * kTileRanks, g1 = min(n, t1 * kTileRanks);
+    if (threadIdx.x < kTilesPerGroup) s_any[threadIdx.x] = 0;
+    const PairWin w = pair_window(start, alen, P, g0, g1 - 1, s_start, s_alen, s_sh);
+    if (w.lds) {
+        for (uint32_t j = threadIdx.x; j < w.k; j += kBlock) s_L[j] = lmax[w.lo + j];
+        __syncthreads();
+    }
+    auto pstart = [&](uint32_t q) { return w.lds ? (uint32_t)s_start[q] : (uint32_t)start[w.lo + q]; };
+    auto pL = [&](uint32_t q) { return w.lds ? s_L[q] : lmax[w.lo + q]; };
+    auto pb = [&](uint32_t q) { return pstart(q) + (w.lds ? (uint32_t)s_alen[q] : (uint32_t)alen[w.lo + q]); };
+
+    uint32_t cur = 0;
     for (uint32_t t = t0; t < t1; ++t) {
         const uint32_t base = t * kTileRanks;
         const uint32_t cnt = min(kTileRanks, n - base);
+        int32_t v[kChunk];
+#pragma unroll
+        for (uint32_t i = 0; i < kChunk; ++i) {
+            const uint32_t j = i * kBlock + threadIdx.x;
+            v[i] = j < cnt ? lcp[base + j] : 0;
+        }
         int any = 0;
 #pragma unroll
         for (uint32_t i = 0; i < kChunk; ++i) {
             const uint32_t j = i * kBlock + threadIdx.x;
-            if (j < cnt) {
-                const int32_t v = lcp[base + j];
-                s_lcp[j] = v;
-                uint32_t p;
-                any |= v > 0 && !run_start(base + j, v, start, P, lmax, &p);
-            }
+            if (j >= cnt || v[i] <= 0) continue;
+            const uint32_t r = base + j;
+            const uint32_t q = pair_at(w, s_start, start, P, r, cur);
+            const uint32_t L = pL(q);
+            any |= r != pstart(q) && L != 0 && (uint32_t)v[i] >= L;
         }
-        any = __syncthreads_or(any);
-        if (!any) {
-            if (threadIdx.x == 0) {
-                const uint32_t r = base + cnt - 1;
-                const int32_t q = sa[r];
-                const uint32_t p = find_pair(start, P, r);
-                ChunkSum c = chunk_empty();
-                c.has_b = 1;
-                c.tail = RunSum{q, in_b(start, alen, p, (uint32_t)q) ? 1 : 0, INT_MAX, -1};
-                total = chunk_combine(total, c, start, P, best);
-            }
-            __syncthreads();
-            continue;
-        }
-#pragma unroll
-        for (uint32_t i = 0; i < kChunk; ++i) {
-            const uint32_t j = i * kBlock + threadIdx.x;
-            if (j < cnt) s_sa[j] = sa[base + j];
-        }
-        __syncthreads();
+        if (__any(any) && (threadIdx.x & 63u) == 0) s_any[t - t0] = 1;   // LDS store; any wave may set it
+    }
+    __syncthreads();
+    if (threadIdx.x < t1 - t0 && !s_any[threadIdx.x]) {
+        // every rank starts a run; only the last run can continue
+        const uint32_t base = (t0 + threadIdx.x) * kTileRanks;
+        const uint32_t r = base + min(kTileRanks, n - base) - 1;
+        const uint32_t p = find_pair(start, P, r);
+        const int32_t x = sa[r];
+        ChunkSum c = chunk_empty();
+        c.has_b = 1;
+        c.tail = RunSum{x, in_b(start, alen, p, (uint32_t)x) ? 1 : 0, INT_MAX, -1};
+        s_tile[threadIdx.x] = c;
+    }
+    for (uint32_t t = t0; t < t1; ++t) {
+        if (!s_any[t - t0]) continue;   // uniform: s_any is final after the barrier above
+        // rare (tiles inside a run of its pair's length): each thread reads its ranks directly
+        const uint32_t base = t * kTileRanks;
+        const uint32_t cnt = min(kTileRanks, n - base);
         ChunkSum c = chunk_empty();
         const uint32_t j0 = threadIdx.x * kChunk;
+        uint32_t c2 = 0;
         for (uint32_t j = j0; j < min(cnt, j0 + kChunk); ++j) {
-            const int32_t q = s_sa[j];
-            uint32_t p;
-            const bool starts = run_start(base + j, s_lcp[j], start, P, lmax, &p);
-            const RunSum e{q, in_b(start, alen, p, (uint32_t)q) ? 1 : 0, INT_MAX, -1};
+            const uint32_t r = base + j;
+            const int32_t x = sa[r];
+            const uint32_t q = w.lds ? pair_at(w, s_start, start, P, r, c2) : find_pair(start, P, r) - w.lo;
+            const uint32_t L = pL(q);
+            const bool starts = r == pstart(q) || L == 0 || (uint32_t)lcp[r] < L;
+            const RunSum e{x, (uint32_t)x > pb(q) ? 1 : 0, INT_MAX, -1};
             if (starts) {
                 if (c.has_b) finalize(c.tail, start, P, best);
                 c.has_b = 1;
@@ -253,10 +349,15 @@ __global__ __launch_bounds__(kBlock) void k_seg_runs(const int32_t *__restrict__
             }
         }
         reduce_chunks(s_sum, c, start, P, best);
-        if (threadIdx.x == 0) total = chunk_combine(total, s_sum[0], start, P, best);
+        if (threadIdx.x == 0) s_tile[t - t0] = s_sum[0];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[blockIdx.x] = total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ChunkSum total = chunk_empty();
+        for (uint32_t t = t0; t < t1; ++t) total = chunk_combine(total, s_tile[t - t0], start, P, best);
+        out[blockIdx.x] = total;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_seg_runs_final(const ChunkSum *__restrict__ in, uint32_t count,
@@ -365,7 +466,7 @@ lor_status batch_overlap_run(const uint8_t *seqs, uint32_t P, uint64_t N, const 
     LOR_HIP(hipMemcpyAsync(src, h_src, 2ull * P * sizeof(int64_t), hipMemcpyHostToDevice, s));
     LOR_TRY(zero_words(hdr, 16, s));
     LOR_LAUNCH("k_join_pairs", 3.0 * N, s,
-               hipLaunchKernelGGL(k_join_pairs, dim3(grid_for(N)), dim3(kBlock), 0, s, seqs, start, alen, src, P,
+               hipLaunchKernelGGL(k_join_pairs, dim3(div_up(N, kJoinTile)), dim3(kBlock), 0, s, seqs, start, alen, src, P,
                                   (uint32_t)N, text, hdr));
     LOR_TRY(dc3_u16(text, (uint32_t)N, 8u * (P - 1) + 6u, sa, ar, hdr, s));
     ar.release(phase);
@@ -377,9 +478,9 @@ lor_status batch_overlap_run(const uint8_t *seqs, uint32_t P, uint64_t N, const 
     LOR_TAKE(ar, ChunkSum, (size_t)groups + 1, sums);
     LOR_LAUNCH("k_pair_init", 8.0 * P, s,
                hipLaunchKernelGGL(k_pair_init, dim3(grid_for(P)), dim3(kBlock), 0, s, P, lmax, best));
-    LOR_LAUNCH("k_seg_max", 8.0 * N, s,
-               hipLaunchKernelGGL(k_seg_max, dim3(grid_for(N)), dim3(kBlock), 0, s, sa, lcp, (uint32_t)N, start, alen,
-                                  P, lmax));
+    LOR_LAUNCH("k_seg_max", 4.0 * N, s,   // LCP; SA only where an LCP can still raise its pair's maximum
+               hipLaunchKernelGGL(k_seg_max, dim3(div_up(N, kTileRanks)), dim3(kBlock), 0, s, sa, lcp, (uint32_t)N,
+                                  start, alen, P, lmax));
     LOR_LAUNCH("k_seg_runs", 4.0 * N, s,
                hipLaunchKernelGGL(k_seg_runs, dim3(groups), dim3(kBlock), 0, s, sa, lcp, (uint32_t)N, start, alen, P,
                                   lmax, best, sums));

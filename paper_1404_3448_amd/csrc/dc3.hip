@@ -287,6 +287,48 @@ __global__ __launch_bounds__(kBlock) void k_presence(const CH *__restrict__ t, D
     }
 }
 
+// Pair-tagged texts: the key is tag * 512 + codes and tags only grow along
+// the text, so the sample positions of one workgroup (q in [q0, q0 + kTagQ))
+// reach a short slice of bitmap words. The slice is marked in LDS and merged
+// into the bitmap once; a key outside it (the padding triple) goes to the
+// bitmap directly, as does everything when the slice is too wide.
+constexpr uint32_t kTagQ = kBlock * 16;
+constexpr uint32_t kTagWords = 4096;
+
+__global__ __launch_bounds__(kBlock) void k_presence_tagged(const uint16_t *__restrict__ t, Dims d, int b,
+                                                            uint32_t *__restrict__ bitmap, uint32_t words) {
+    __shared__ uint32_t s_bits[kTagWords];
+    const uint32_t q0 = blockIdx.x * kTagQ;
+    if (q0 >= d.n0) return;
+    const uint32_t q1 = min(d.n0, q0 + kTagQ);
+    const uint32_t w_lo = (sym(t, d.n, min(3u * q0 + 1u, d.n - 1u)) >> 3) * 16u;
+    const uint32_t w_hi = ((sym(t, d.n, min(3u * q1 + 1u, d.n - 1u)) >> 3) + 1u) * 16u;   // exclusive
+    const bool local = w_hi > w_lo && w_hi - w_lo <= kTagWords;
+    if (local) {
+        for (uint32_t w = threadIdx.x; w < w_hi - w_lo; w += kBlock) s_bits[w] = 0;
+        __syncthreads();
+    }
+    for (uint32_t q = q0 + threadIdx.x; q < q1; q += kBlock) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if (c == 1 && q >= d.n2) break;
+            const uint32_t key = Triple<uint16_t>::template pack<uint32_t>(t, d, b, 3u * q + 1u + c);
+            const uint32_t w = key >> 5, bit = 1u << (key & 31u);
+            if (w >= words) continue;
+            if (local && w >= w_lo && w < w_hi) {
+                if (!(s_bits[w - w_lo] & bit)) atomicOr(&s_bits[w - w_lo], bit);
+            } else if (!(bitmap[w] & bit)) {
+                atomicOr(&bitmap[w], bit);
+            }
+        }
+    }
+    if (local) {
+        __syncthreads();
+        for (uint32_t w = threadIdx.x; w < w_hi - w_lo; w += kBlock)
+            if (s_bits[w]) atomicOr(&bitmap[w_lo + w], s_bits[w]);
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_popc(const uint32_t *__restrict__ bitmap, uint32_t words,
                                                  uint32_t *__restrict__ cnt) {
     for (uint32_t w = blockIdx.x * kBlock + threadIdx.x; w < words; w += gridDim.x * kBlock)
@@ -815,9 +857,14 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
         }
         if (!windowed) {
             const int in_lds = words <= 8192;
-            LOR_LAUNCH("k_presence", (double)n * sizeof(CH), s,
-                       hipLaunchKernelGGL(k_presence<CH>, dim3(in_lds ? min(grid_for(d.m), 2048u) : grid_for(d.m)),
-                                          dim3(kBlock), in_lds ? words * 4 : 0, s, t, d, b, bitmap, words, in_lds));
+            if (sizeof(CH) == 2 && !in_lds)
+                LOR_LAUNCH("k_presence", (double)n * sizeof(CH), s,
+                           hipLaunchKernelGGL(k_presence_tagged, dim3(div_up(d.n0, kTagQ)), dim3(kBlock), 0, s,
+                                              reinterpret_cast<const uint16_t *>(t), d, b, bitmap, words));
+            else
+                LOR_LAUNCH("k_presence", (double)n * sizeof(CH), s,
+                           hipLaunchKernelGGL(k_presence<CH>, dim3(in_lds ? min(grid_for(d.m), 2048u) : grid_for(d.m)),
+                                              dim3(kBlock), in_lds ? words * 4 : 0, s, t, d, b, bitmap, words, in_lds));
             LOR_LAUNCH("k_popc", 8.0 * words, s,
                        hipLaunchKernelGGL(k_popc, dim3(grid_for(words)), dim3(kBlock), 0, s, bitmap, words, below));
             LOR_TRY(scan_exclusive(below, words, stmp, hdr + 1, s));
