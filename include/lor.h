@@ -112,7 +112,11 @@ lor_status lor_build_lcp(const uint8_t *text, int64_t n, const int32_t *sa,
  * sparse table: level k (1 <= k <= levels = floor(log2 n)) holds, for every
  * i with i + 2^k <= n, the minimum of LCP[i .. i + 2^k). Level 0 is the LCP
  * array itself and is not copied. The table memory is caller-owned; the
- * handle is plain data that records where the levels are. */
+ * handle is plain data that records where the levels are. The buffer starts
+ * with a 256-byte header that the build fills (the largest LCP value);
+ * when that value is at most 65535 the levels are stored as 16-bit entries,
+ * otherwise as 32-bit ones. The kernels read the header themselves (no host
+ * round trip), so answers do not depend on the width. */
 typedef struct {
     int32_t *table;      /* device memory holding the levels */
     int64_t n;           /* length of the LCP array */
@@ -120,7 +124,8 @@ typedef struct {
     int32_t kind;        /* 0: full sparse table, 1: compact block table */
 } lor_rmq;
 
-/* Bytes of levels 1..floor(log2 n). */
+/* Bytes of the header plus levels 1..floor(log2 n) at 32 bits per entry
+ * (0 when n < 2: queries then need no table). */
 size_t lor_rmq_bytes(int64_t n);
 lor_status lor_rmq_build(const int32_t *lcp, int64_t n, void *table, size_t table_bytes,
                          lor_rmq *out, void *hip_stream);

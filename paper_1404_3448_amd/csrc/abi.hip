@@ -321,7 +321,7 @@ lor_status lor_build_lcp(const uint8_t *text, int64_t n, const int32_t *sa, int3
 size_t lor_rmq_bytes(int64_t n) {
     if (n < 2 || n > INT32_MAX) return 0;
     const int levels = bits_for((uint64_t)n) - 1;
-    return (size_t)rmq_level_offset((uint64_t)n, levels + 1) * sizeof(int32_t);
+    return ((size_t)kRmqHeaderWords + (size_t)rmq_level_offset((uint64_t)n, levels + 1)) * sizeof(int32_t);
 }
 
 lor_status lor_rmq_build(const int32_t *lcp, int64_t n, void *table, size_t table_bytes, lor_rmq *out,
@@ -340,7 +340,7 @@ lor_status lor_rmq_build(const int32_t *lcp, int64_t n, void *table, size_t tabl
         return LOR_EWORKSPACE;
     }
     const int levels = n >= 2 ? bits_for((uint64_t)n) - 1 : 0;
-    LOR_TRY(rmq_build_levels(lcp, (uint32_t)n, static_cast<int32_t *>(table), levels, (hipStream_t)hip_stream));
+    LOR_TRY(rmq_build_full(lcp, (uint32_t)n, static_cast<int32_t *>(table), levels, (hipStream_t)hip_stream));
     out->table = static_cast<int32_t *>(table);
     out->n = n;
     out->levels = levels;

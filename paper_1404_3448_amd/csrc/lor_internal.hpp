@@ -237,8 +237,18 @@ lor_status lcp_build_u16(const uint16_t *text, uint32_t n, const int32_t *sa, in
                          Arena &ar, hipStream_t s);
 
 // ------------------------------------------------------------------ RMQ
+// A full table is a header of kRmqHeaderWords words (word 0: the largest LCP
+// value) followed by the levels: 16-bit entries when that value is at most
+// 65535, else 32-bit; the buffer is sized for 32-bit entries.
+constexpr uint32_t kRmqHeaderWords = 64;
 uint64_t rmq_level_offset(uint64_t n, int level);   // entries before `level` (levels from 1)
-lor_status rmq_build_levels(const int32_t *lcp, uint32_t n, int32_t *table, int levels, hipStream_t s);
+// Levels 1..levels of a sparse table over lcp[0..n) into `table` (level
+// storage); hdr: the header that sets the width, or nullptr for 32-bit; eb:
+// entry bytes, for the per-kernel byte accounting only.
+lor_status rmq_build_levels(const int32_t *lcp, uint32_t n, int32_t *table, int levels, hipStream_t s,
+                            const uint32_t *hdr, int eb);
+// The full table with its header: largest LCP, then the levels.
+lor_status rmq_build_full(const int32_t *lcp, uint32_t n, int32_t *buffer, int levels, hipStream_t s);
 // Compact table: block minima of 64-entry blocks, then levels 1..levels
 // over the blocks. Entries in total (and the level count via *levels).
 uint64_t rmq_compact_blocks(uint64_t n);
@@ -247,7 +257,7 @@ lor_status rmq_build_compact(const int32_t *lcp, uint32_t n, int32_t *table, hip
 lor_status rmq_queries_compact(const int32_t *table, uint32_t n, int levels, const int32_t *lcp, const int32_t *isa,
                                int mode, const int32_t *qi, const int32_t *qj, uint32_t nq, int32_t *min_out,
                                int32_t *argmin_out, hipStream_t s);
-lor_status rmq_queries(const int32_t *table, uint32_t n, int levels, const int32_t *lcp,
+lor_status rmq_queries(int32_t *buffer, uint32_t n, int levels, const int32_t *lcp,
                        const int32_t *isa, int mode, const int32_t *qi, const int32_t *qj,
                        uint32_t nq, int32_t *min_out, int32_t *argmin_out, hipStream_t s);
 

@@ -15,6 +15,11 @@
 // written once. With 288 GB of HBM the table fits next to
 // the 1G-suffix arrays, and every query costs four independent gathers
 // (two ISA entries, two table entries) instead of a pointer walk.
+// Levels hold minima of LCP values, so when the largest LCP is at most
+// 65535 (a reduction pass writes it into the table's header first) every
+// level is stored as 16-bit entries: half the bytes to write and read. The
+// kernels read the header and pick the width themselves, so nothing waits
+// on the host.
 #include <climits>
 
 #include "lor_internal.hpp"
@@ -33,8 +38,31 @@ namespace {
 constexpr uint32_t kLvItems = 16;
 constexpr uint32_t kLvTile = kBlock * kLvItems;
 
-__global__ __launch_bounds__(kBlock) void k_st_level(const int32_t *__restrict__ prev, uint32_t half,
-                                                     uint32_t cnt, uint32_t tiles, int32_t *__restrict__ cur) {
+// Level storage of a table: entries from `base` on, 16-bit when the header
+// word says every LCP value fits (hdr == nullptr: always 32-bit).
+struct TabView {
+    int32_t *w32;
+    uint16_t *w16;
+    bool narrow;
+    __device__ __forceinline__ int32_t get(uint64_t i) const { return narrow ? (int32_t)w16[i] : w32[i]; }
+    __device__ __forceinline__ void put(uint64_t i, int32_t v) const {
+        if (narrow) w16[i] = (uint16_t)v;
+        else w32[i] = v;
+    }
+};
+
+__device__ __forceinline__ TabView tab_view(int32_t *base, const uint32_t *hdr) {
+    TabView t;
+    t.w32 = base;
+    t.w16 = reinterpret_cast<uint16_t *>(base);
+    t.narrow = hdr != nullptr && hdr[0] <= 65535u;
+    return t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_st_level(int32_t *__restrict__ base, const uint32_t *__restrict__ hdr,
+                                                     uint64_t prev_off, uint64_t cur_off, uint32_t half,
+                                                     uint32_t cnt, uint32_t tiles) {
+    const TabView tv = tab_view(base, hdr);
     const uint32_t per = (tiles + kXcds - 1) / kXcds;
     const uint32_t j = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;   // place in the sequence
     if (blockIdx.x / kXcds >= per || j >= tiles) return;
@@ -49,13 +77,13 @@ __global__ __launch_bounds__(kBlock) void k_st_level(const int32_t *__restrict__
 #pragma unroll
     for (int r = 0; r < (int)kLvItems; ++r) {
         const uint32_t i = i0 + r * kBlock;
-        a[r] = i < cnt ? prev[i] : 0;
-        b[r] = i < cnt ? prev[i + half] : 0;
+        a[r] = i < cnt ? tv.get(prev_off + i) : 0;
+        b[r] = i < cnt ? tv.get(prev_off + i + half) : 0;
     }
 #pragma unroll
     for (int r = 0; r < (int)kLvItems; ++r) {
         const uint32_t i = i0 + r * kBlock;
-        if (i < cnt) cur[i] = min(a[r], b[r]);
+        if (i < cnt) tv.put(cur_off + i, min(a[r], b[r]));
     }
 }
 
@@ -70,9 +98,11 @@ __device__ __forceinline__ uint64_t level_offset_dev(uint64_t n, int level);
 // P is read from HBM about once for all NL levels (instead of twice per
 // level); the writes are the table itself.
 template <int NL, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_st_chain(const int32_t *__restrict__ P, uint32_t cnt_p, uint32_t n,
-                                                     int k, uint32_t H, uint32_t nb, uint32_t steps,
-                                                     int32_t *__restrict__ table) {
+__global__ __launch_bounds__(kBlock) void k_st_chain(int32_t *__restrict__ table, const uint32_t *__restrict__ hdr,
+                                                     uint32_t cnt_p, uint32_t n, int k, uint32_t H, uint32_t nb,
+                                                     uint32_t steps) {
+    const TabView tv = tab_view(table, hdr);
+    const uint64_t p_off = level_offset_dev(n, k - 1);   // level k-1 (k >= 2)
     constexpr int W = 1 << NL;
     constexpr uint32_t B = kBlock * ITEMS;
     const uint32_t c = blockIdx.x % H;
@@ -86,7 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_st_chain(const int32_t *__restrict__
 #pragma unroll
         for (int r = 0; r < ITEMS; ++r) {
             const uint64_t idx = base + (uint64_t)r * kBlock;
-            dst[r] = idx < cnt_p ? P[idx] : INT_MAX;
+            dst[r] = idx < cnt_p ? tv.get(p_off + idx) : INT_MAX;
         }
     };
 #pragma unroll
@@ -103,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void k_st_chain(const int32_t *__restrict__
 #pragma unroll
                 for (int u = 1 << a; u < (2 << a); ++u) m = min(m, win[u][r]);
                 const int lv = k + a;
-                if (i < (uint64_t)n - (1ull << lv) + 1) table[level_offset_dev(n, lv) + i] = m;
+                if (i < (uint64_t)n - (1ull << lv) + 1) tv.put(level_offset_dev(n, lv) + i, m);
             }
         }
 #pragma unroll
@@ -123,8 +153,10 @@ constexpr uint32_t kRmqBlock = 64;          // LCP entries per block of the comp
 // Levels k0 .. k0+nl-1 from level k0-1 (`prev`, prev_count entries) for the
 // outputs [i0, i0 + kStTile) of this workgroup.
 __global__ __launch_bounds__(kBlock) void k_st_fused(const int32_t *__restrict__ prev, uint32_t prev_count,
-                                                     uint32_t n, int k0, int nl, int32_t *__restrict__ table) {
+                                                     uint32_t n, int k0, int nl, int32_t *__restrict__ table,
+                                                     const uint32_t *__restrict__ hdr) {
     extern __shared__ int32_t s_buf[];
+    const TabView tv = tab_view(table, hdr);
     const uint32_t halo = (1u << (k0 - 1)) * ((1u << nl) - 1u);
     const uint32_t span = kStTile + halo;
     int32_t *b0 = s_buf, *b1 = s_buf + span;
@@ -142,10 +174,10 @@ __global__ __launch_bounds__(kBlock) void k_st_fused(const int32_t *__restrict__
         for (uint32_t j = threadIdx.x; j < valid; j += kBlock) b1[j] = min(b0[j], b0[j + half]);
         __syncthreads();
         const uint32_t count = n - (1u << k) + 1u;
-        int32_t *out = table + level_offset_dev(n, k);
+        const uint64_t off = level_offset_dev(n, k);
         for (uint32_t j = threadIdx.x; j < kStTile; j += kBlock) {
             const uint32_t i = i0 + j;
-            if (i < count) out[i] = b1[j];
+            if (i < count) tv.put(off + i, b1[j]);
         }
         int32_t *x = b0; b0 = b1; b1 = x;
         __syncthreads();
@@ -154,7 +186,8 @@ __global__ __launch_bounds__(kBlock) void k_st_fused(const int32_t *__restrict__
 
 struct Levels {
     const int32_t *lcp;
-    const int32_t *table;
+    int32_t *table;          // level storage (after the header)
+    const uint32_t *hdr;     // the header
     uint32_t n;
     int levels;
 };
@@ -165,22 +198,22 @@ __device__ __forceinline__ uint64_t level_offset_dev(uint64_t n, int level) {
     return k * (n + 1) - ((2ull << k) - 2ull);
 }
 
-__device__ __forceinline__ const int32_t *level_ptr(const Levels &L, int k) {
-    return k == 0 ? L.lcp : L.table + level_offset_dev(L.n, k);
+// Entry i of level k (level 0 is the LCP array).
+__device__ __forceinline__ int32_t level_at(const Levels &L, const TabView &tv, int k, uint32_t i) {
+    return k == 0 ? L.lcp[i] : tv.get(level_offset_dev(L.n, k) + i);
 }
 
 // min of a[lo..hi] (lo <= hi) and, when want_pos, its leftmost position.
-__device__ __forceinline__ int32_t range_min(const Levels &L, uint32_t lo, uint32_t hi, bool want_pos,
-                                             int32_t *pos) {
+__device__ __forceinline__ int32_t range_min(const Levels &L, const TabView &tv, uint32_t lo, uint32_t hi,
+                                             bool want_pos, int32_t *pos) {
     const uint32_t len = hi - lo + 1;
     const int k = 31 - __builtin_clz(len);
-    const int32_t *lv = level_ptr(L, k);
-    const int32_t v = min(lv[lo], lv[hi + 1 - (1u << k)]);
+    const int32_t v = min(level_at(L, tv, k, lo), level_at(L, tv, k, hi + 1 - (1u << k)));
     if (want_pos) {
         uint32_t p = lo;
         for (int kk = k; kk >= 0; --kk) {
             const uint32_t w = 1u << kk;
-            if (p + w - 1 <= hi && level_ptr(L, kk)[p] > v) p += w;
+            if (p + w - 1 <= hi && level_at(L, tv, kk, p) > v) p += w;
         }
         *pos = (int32_t)p;
     }
@@ -191,11 +224,13 @@ __global__ __launch_bounds__(kBlock) void k_query(Levels L, const int32_t *__res
                                                   const int32_t *__restrict__ qi, const int32_t *__restrict__ qj,
                                                   uint32_t nq, int32_t *__restrict__ out_min,
                                                   int32_t *__restrict__ out_arg) {
+    const TabView tv = tab_view(L.table, L.levels > 0 ? L.hdr : nullptr);
     for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < nq; q += gridDim.x * kBlock) {
         const int32_t a = qi[q], b = qj[q];
         int32_t v = -1, pos = -1;
         if (mode == 0) {
-            if (a >= 0 && b >= a && (uint32_t)b < L.n) v = range_min(L, (uint32_t)a, (uint32_t)b, out_arg != nullptr, &pos);
+            if (a >= 0 && b >= a && (uint32_t)b < L.n)
+                v = range_min(L, tv, (uint32_t)a, (uint32_t)b, out_arg != nullptr, &pos);
         } else if (a >= 0 && b >= 0 && (uint32_t)a < L.n && (uint32_t)b < L.n) {
             if (a == b) {
                 v = (int32_t)(L.n - (uint32_t)a);
@@ -203,13 +238,37 @@ __global__ __launch_bounds__(kBlock) void k_query(Levels L, const int32_t *__res
                 const int32_t ra = isa[a], rb = isa[b];
                 if (ra != rb && (uint32_t)ra < L.n && (uint32_t)rb < L.n) {
                     const uint32_t lo = (uint32_t)min(ra, rb) + 1u, hi = (uint32_t)max(ra, rb);
-                    v = range_min(L, lo, hi, out_arg != nullptr, &pos);
+                    v = range_min(L, tv, lo, hi, out_arg != nullptr, &pos);
                 }
             }
         }
         out_min[q] = v;
         if (out_arg) out_arg[q] = pos;
     }
+}
+
+// Largest LCP value into hdr[0] (zeroed before): a grid of at most
+// kMaxGrid workgroups, each reducing in registers and LDS, then one atomic
+// per workgroup (skipped when the published value is already as large).
+constexpr uint32_t kMaxGrid = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_lcp_max(const int32_t *__restrict__ lcp, uint32_t n,
+                                                    uint32_t *__restrict__ hdr) {
+    __shared__ uint32_t s_red[kBlock / kWave];
+    uint32_t m = 0;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        m = max(m, (uint32_t)max(lcp[i], 0));
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+    if ((threadIdx.x & 63u) == 0) s_red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / kWave; ++w) m = max(m, s_red[w]);
+        if (m > __hip_atomic_load(hdr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(hdr, m);
+    }
+}
+
+__global__ __launch_bounds__(kWave) void k_hdr_zero(uint32_t *hdr) {
+    if (threadIdx.x < kRmqHeaderWords) hdr[threadIdx.x] = 0;
 }
 
 // ------------------------------------------------------ compact variant
@@ -336,7 +395,7 @@ lor_status rmq_build_compact(const int32_t *lcp, uint32_t n, int32_t *table, hip
     LOR_LAUNCH("k_block_min", 4.0 * n + 4.0 * nb, s,
                hipLaunchKernelGGL(k_block_min, dim3(div_up((uint64_t)nb * kWave, kBlock)), dim3(kBlock), 0, s, lcp,
                                   n, nb, table));
-    return rmq_build_levels(table, nb, table + nb, L, s);
+    return rmq_build_levels(table, nb, table + nb, L, s, nullptr, 4);
 }
 
 lor_status rmq_queries_compact(const int32_t *table, uint32_t n, int levels, const int32_t *lcp, const int32_t *isa,
@@ -355,35 +414,54 @@ uint64_t rmq_level_offset(uint64_t n, int level) {
     return k * (n + 1) - ((2ull << k) - 2ull);
 }
 
-lor_status rmq_build_levels(const int32_t *lcp, uint32_t n, int32_t *table, int levels, hipStream_t s) {
+lor_status rmq_build_full(const int32_t *lcp, uint32_t n, int32_t *buffer, int levels, hipStream_t s) {
+    if (levels <= 0) return LOR_OK;
+    uint32_t *hdr = reinterpret_cast<uint32_t *>(buffer);
+    LOR_LAUNCH("k_hdr_zero", 4.0 * kRmqHeaderWords, s,
+               hipLaunchKernelGGL(k_hdr_zero, dim3(1), dim3(kWave), 0, s, hdr));
+    LOR_LAUNCH("k_lcp_max", 4.0 * n, s,
+               hipLaunchKernelGGL(k_lcp_max, dim3(min(grid_for(n), kMaxGrid)), dim3(kBlock), 0, s, lcp, n, hdr));
+    // The width is the kernels' own decision; only per-kernel byte accounting
+    // (timing on) reads it back, to count the entry size the levels really use.
+    int eb = 4;
+    if (timing_on()) {
+        uint32_t mx = 0;
+        LOR_HIP(hipMemcpyAsync(&mx, hdr, sizeof(mx), hipMemcpyDeviceToHost, s));
+        LOR_HIP(hipStreamSynchronize(s));
+        eb = mx <= 65535u ? 2 : 4;
+    }
+    return rmq_build_levels(lcp, n, buffer + kRmqHeaderWords, levels, s, hdr, eb);
+}
+
+lor_status rmq_build_levels(const int32_t *lcp, uint32_t n, int32_t *table, int levels, hipStream_t s,
+                            const uint32_t *hdr, int eb) {
     int k = 1;
     while (k <= levels && k <= kStFusedTop) {
         const int nl = min(kStFuse, min(levels, kStFusedTop) - k + 1);
-        const int32_t *prev = k == 1 ? lcp : table + rmq_level_offset(n, k - 1);
+        const int32_t *prev = lcp;   // k == 1: the fused pass starts from level 0
         const uint32_t prev_count = n - (1u << (k - 1)) + 1u;
         const uint32_t count = n - (1u << k) + 1u;
         const uint32_t halo = (1u << (k - 1)) * ((1u << nl) - 1u);
         const size_t lds = 2 * (size_t)(kStTile + halo) * sizeof(int32_t);
         double bytes = 0;
-        for (int l = 0; l < nl; ++l) bytes += 4.0 * (n - (1u << (k + l)) + 1u);
+        for (int l = 0; l < nl; ++l) bytes += (double)eb * (n - (1u << (k + l)) + 1u);
         bytes += 4.0 * prev_count;
         LOR_LAUNCH("k_st_fused", bytes, s,
                    hipLaunchKernelGGL(k_st_fused, dim3(div_up(count, kStTile)), dim3(kBlock), lds, s, prev,
-                                      prev_count, n, k, nl, table));
+                                      prev_count, n, k, nl, table, hdr));
         k += nl;
     }
     while (k <= levels) {
-        const int32_t *prev = table + rmq_level_offset(n, k - 1);
         const uint32_t half = 1u << (k - 1);
         const int nl = min(3, levels - k + 1);
         const uint32_t items = half >= kBlock * 16u && nl < 3 ? 16u : (half >= kBlock * 8u ? 8u : 4u);
         if (nl == 1 || half < kBlock * 4u) {
-            int32_t *cur = table + rmq_level_offset(n, k);
             const uint32_t cnt = n - (1u << k) + 1u;
             const uint32_t tiles = div_up(cnt, kLvTile);
-            LOR_LAUNCH("k_st_level", (double)cnt * 8, s,
-                       hipLaunchKernelGGL(k_st_level, dim3(kXcds * div_up(tiles, kXcds)), dim3(kBlock), 0, s, prev,
-                                          half, cnt, tiles, cur));
+            LOR_LAUNCH("k_st_level", (double)cnt * 2 * eb, s,
+                       hipLaunchKernelGGL(k_st_level, dim3(kXcds * div_up(tiles, kXcds)), dim3(kBlock), 0, s, table,
+                                          hdr, rmq_level_offset(n, k - 1), rmq_level_offset(n, k), half, cnt,
+                                          tiles));
             ++k;
             continue;
         }
@@ -391,13 +469,13 @@ lor_status rmq_build_levels(const int32_t *lcp, uint32_t n, int32_t *table, int 
         const uint32_t cnt_p = n - half + 1u;
         const uint32_t nb = div_up(n - (1u << k) + 1u, B);   // blocks holding level-k outputs
         const uint32_t segs = div_up(div_up(nb, H), kChainSteps);
-        double bytes = 4.0 * cnt_p;
-        for (int a = 0; a < nl; ++a) bytes += 4.0 * (n - (1u << (k + a)) + 1u);
+        double bytes = (double)eb * cnt_p;
+        for (int a = 0; a < nl; ++a) bytes += (double)eb * (n - (1u << (k + a)) + 1u);
         const dim3 grid(H * segs);
 #define LOR_CHAIN(NL, IT)                                                                                   \
     LOR_LAUNCH("k_st_chain", bytes, s,                                                                      \
-               hipLaunchKernelGGL((k_st_chain<NL, IT>), grid, dim3(kBlock), 0, s, prev, cnt_p, n, k, H, nb, \
-                                  kChainSteps, table))
+               hipLaunchKernelGGL((k_st_chain<NL, IT>), grid, dim3(kBlock), 0, s, table, hdr, cnt_p, n, k, H, \
+                                  nb, kChainSteps))
         if (nl == 3) {
             if (items == 4) LOR_CHAIN(3, 4);
             else LOR_CHAIN(3, 8);
@@ -412,11 +490,12 @@ lor_status rmq_build_levels(const int32_t *lcp, uint32_t n, int32_t *table, int 
     return LOR_OK;
 }
 
-lor_status rmq_queries(const int32_t *table, uint32_t n, int levels, const int32_t *lcp, const int32_t *isa,
+lor_status rmq_queries(int32_t *buffer, uint32_t n, int levels, const int32_t *lcp, const int32_t *isa,
                        int mode, const int32_t *qi, const int32_t *qj, uint32_t nq, int32_t *min_out,
                        int32_t *argmin_out, hipStream_t s) {
     if (nq == 0) return LOR_OK;
-    Levels L{lcp, table, n, levels};
+    Levels L{lcp, levels > 0 ? buffer + kRmqHeaderWords : nullptr, reinterpret_cast<const uint32_t *>(buffer), n,
+             levels};
     LOR_LAUNCH("k_query", (double)nq * (mode ? 28 : 20), s,
                hipLaunchKernelGGL(k_query, dim3(grid_for(nq)), dim3(kBlock), 0, s, L, isa, mode, qi, qj, nq,
                                   min_out, argmin_out));

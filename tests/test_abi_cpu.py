@@ -80,11 +80,12 @@ def test_other_argument_errors(L):
 
 def test_size_queries():
     n = (1 << 30) + 16
+    hdr = 64                                              # header words (the largest LCP value, width)
     assert lor.lor_rmq_bytes(1) == 0
-    assert lor.lor_rmq_bytes(2) == 4                      # one level, one window
-    assert lor.lor_rmq_bytes(5) == 4 * ((5 - 1) + (5 - 3))
+    assert lor.lor_rmq_bytes(2) == 4 * (hdr + 1)          # one level, one window
+    assert lor.lor_rmq_bytes(5) == 4 * (hdr + (5 - 1) + (5 - 3))
     levels = n.bit_length() - 1
-    assert lor.lor_rmq_bytes(n) == 4 * sum(n - (1 << k) + 1 for k in range(1, levels + 1))
+    assert lor.lor_rmq_bytes(n) == 4 * (hdr + sum(n - (1 << k) + 1 for k in range(1, levels + 1)))
     # the DC3 workspace grows linearly (a bound of the level footprints)
     a = lor.lor_build_sa_workspace(1 << 20, 2)
     b = lor.lor_build_sa_workspace(1 << 24, 2)

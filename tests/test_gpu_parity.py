@@ -351,6 +351,33 @@ def test_long_text_1g_full_size():
     assert np.array_equal(got_h[pick], want)
 
 
+@pytest.mark.parametrize("top", [65535, 65536, 3_000_000])
+def test_rmq_table_width_boundary(top):
+    """Levels are stored as 16-bit entries only when the largest LCP value is
+    at most 65535: at 65535 (16-bit), 65536 and 3M (32-bit) every level of
+    an 18-level table (fused, chained and single-level passes) answers as
+    the plain minimum does, with the leftmost position."""
+    n = 300_007
+    say("rmq width", top)
+    rng = np.random.default_rng(top)
+    lcp_h = rng.integers(0, 70000, size=n).astype(np.int64)
+    lcp_h = np.minimum(lcp_h, top).astype(np.int32)
+    lcp_h[rng.integers(0, n)] = top
+    lcp = dev(lcp_h)
+    rmq = lor.lor_rmq_build(lcp)
+    lo = rng.integers(0, n, size=6000)
+    span = np.where(rng.random(6000) < 0.5, rng.integers(0, 5000, size=6000), rng.integers(0, n, size=6000))
+    hi = np.minimum(n - 1, lo + span)
+    m, a = lor.lor_rmq_query(rmq, lcp, None, 0, dev(lo.astype(np.int32)), dev(hi.astype(np.int32)),
+                             want_argmin=True)
+    m, a = host(m), host(a)
+    for k in range(0, lo.size, 3):
+        assert (m[k], a[k]) == oracle.range_min(lcp_h, lo[k], hi[k]), k
+    whole = lor.lor_rmq_query(rmq, lcp, None, 0, dev(np.array([0], np.int32)),
+                              dev(np.array([n - 1], np.int32)), want_argmin=True)
+    assert (host(whole[0])[0], host(whole[1])[0]) == oracle.range_min(lcp_h, 0, n - 1)
+
+
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 127, 128, 129, 191, 1000, 4097, 100003])
 @pytest.mark.parametrize("values", [2, 50, 1 << 20])
 def test_rmq_compact_equals_oracle_and_full_table(n, values):
