@@ -72,6 +72,18 @@ def test_batched_tiny_pairs_brute_force():
         assert got[p] == brute.longest_overlap([a, b]), p
 
 
+def test_batched_many_minimal_pairs():
+    """8000 pairs of 0-2 bases: a 4096-rank tile then spans more pairs than a
+    workgroup keeps in LDS, so the join, the per-pair maximum, the run pass and
+    the level-0 naming all take their search-over-all-pairs paths."""
+    rng = np.random.default_rng(78)
+    pairs = [(rng.integers(0, 2, size=int(rng.integers(0, 3)), dtype=np.uint8),
+              rng.integers(0, 2, size=int(rng.integers(0, 3)), dtype=np.uint8)) for _ in range(8000)]
+    got = run_batched(pairs)
+    for p, (a, b) in enumerate(pairs):
+        assert got[p] == brute.longest_overlap([a, b]), p
+
+
 def test_batched_equals_plain_path():
     ws = synth.batched_pairs(seed=11, num_pairs=24, lo=1e3, hi=2e5)
     pairs = [tuple(w.seqs) for w in ws]
