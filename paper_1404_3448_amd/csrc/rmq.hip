@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_st_chain(int32_t *__restrict__ table
 
 constexpr uint32_t kChainSteps = 64;        // blocks per workgroup along a column
 
-constexpr uint32_t kStTile = kBlock * 16;   // outputs per workgroup in fused levels
+constexpr uint32_t kStTile = kBlock * 8;    // outputs per workgroup in fused levels
 constexpr int kStFuse = 10;                 // levels per fused pass
 constexpr int kStFusedTop = 10;             // levels 1..10 are built in LDS (halo < 1024 entries)
 constexpr uint32_t kRmqBlock = 64;          // LCP entries per block of the compact table
