@@ -143,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_st_chain(int32_t *__restrict__ table
     }
 }
 
-constexpr uint32_t kChainSteps = 64;        // blocks per workgroup along a column
+constexpr uint32_t kChainSteps = 8;         // blocks per workgroup along a column (8 beat 4, 16, 32 and 64)
 
 constexpr uint32_t kStTile = kBlock * 8;    // outputs per workgroup in fused levels
 constexpr int kStFuse = 10;                 // levels per fused pass
