@@ -33,7 +33,8 @@ namespace lor {
 
 namespace {
 
-constexpr int kScanItems = 8;                         // consecutive items per thread in scan-emit kernels
+constexpr int kScanItems = 4;                         // consecutive items per thread in scan-emit kernels
+static_assert(kScanItems % 4 == 0, "k_ns_write reads a thread's items as 16-byte LDS groups");
 constexpr uint32_t kScanTile = kBlock * kScanItems;
 constexpr uint32_t kMaxScanGroups = 4096;
 
