@@ -36,7 +36,7 @@ namespace {
 constexpr int kDigitBits = 8;
 constexpr int kBins = 1 << kDigitBits;
 constexpr uint32_t kMinTile = kBlock * 8;   // smallest tile of any plan (sizes the count table)
-constexpr uint32_t kColChunks = 1024;       // row chunks of the column scan (4 per scan thread)
+constexpr uint32_t kColChunks = 2048;       // row chunks of the column scan (8 per scan thread)
 
 // Tile handled by this workgroup: XCD x = blockIdx mod 8 takes the x-th
 // eighth of the tiles, in workgroup order. Returns false for the padding
