@@ -361,44 +361,4 @@ lor_status refq_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t Q,
     return LOR_OK;
 }
 
-size_t matrix_workspace(uint64_t n, uint32_t k) {
-    const uint32_t tiles = div_up(n ? n : 1, kRqTile);
-    Arena ar;   // measuring
-    ar.top = kHeaderBytes;
-    ar.take<int32_t>((size_t)k + 1);
-    ar.take<unsigned long long>((size_t)k * k);
-    ar.take<Fwd>(tiles);
-    ar.take<Bwd>(tiles);
-    return ar.top + 1024;
-}
-
-lor_status overlap_matrix(const int32_t *sa, const int32_t *lcp, uint32_t n, const int64_t *offsets, uint32_t k,
-                          lor_overlap *out, void *ws, size_t ws_bytes, hipStream_t s) {
-    std::vector<int32_t> h_start(k + 1);
-    for (uint32_t j = 0; j <= k; ++j) h_start[j] = (int32_t)(offsets[j] + j);
-    Arena ar;
-    ar.base = static_cast<char *>(ws);
-    ar.cap = ws_bytes;
-    ar.top = kHeaderBytes;
-    const uint32_t tiles = div_up(n ? n : 1, kRqTile);
-    int32_t *start;
-    unsigned long long *best;
-    Fwd *tf;
-    Bwd *tb;
-    LOR_TAKE(ar, int32_t, (size_t)k + 1, start);
-    LOR_TAKE(ar, unsigned long long, (size_t)k * k, best);
-    LOR_TAKE(ar, Fwd, tiles, tf);
-    LOR_TAKE(ar, Bwd, tiles, tb);
-    LOR_HIP(hipMemcpyAsync(start, h_start.data(), (k + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    LOR_LAUNCH("k_rq_init", 40.0 * k * k, s,
-               hipLaunchKernelGGL(k_rq_init, dim3(grid_for((uint64_t)k * k)), dim3(kBlock), 0, s, k * k, best, out));
-    if (n > 0)
-        for (uint32_t t = 0; t < k; ++t) {
-            const Target tg{(uint32_t)h_start[t], (uint32_t)h_start[t + 1] - 1u, t};
-            LOR_TRY(target_scan(sa, lcp, n, tg, start, k, k, (int32_t)t, tf, tb, best, out, s));
-        }
-    LOR_HIP(hipStreamSynchronize(s));   // the host table must outlive its copy
-    return LOR_OK;
-}
-
 }  // namespace lor

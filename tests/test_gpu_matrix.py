@@ -80,3 +80,75 @@ def test_matrix_noncoding():
         p = int(rng.integers(0, seqs[i].size))
         seqs[i] = np.concatenate([seqs[i][:p], seg, seqs[i][p:]])
     check(seqs)
+
+
+def first_shared_window(a, b, L):
+    """Smallest o with a[o:o+L] a substring of b (-1: none): polynomial
+    hashes of every length-L window mod 2^64 as candidates, each candidate
+    then compared base by base."""
+    B = np.uint64(0x9E3779B97F4A7C15)
+    Binv = np.uint64(pow(int(B), -1, 1 << 64))
+
+    def windows(s):
+        n = s.size - L + 1
+        if n <= 0:
+            return np.zeros(0, np.uint64)
+        with np.errstate(over="ignore"):
+            pw = np.cumprod(np.full(s.size, B, np.uint64)) * Binv        # B^j
+            iw = np.cumprod(np.full(n, Binv, np.uint64)) * B             # B^-i
+            pre = np.concatenate([[np.uint64(0)], np.cumsum((s.astype(np.uint64) + np.uint64(1)) * pw)])
+            return (pre[L:] - pre[:n]) * iw
+    hb = windows(b)
+    ha = windows(a)
+    if not ha.size or not hb.size:
+        return -1
+    for o in np.flatnonzero(np.isin(ha, hb)).tolist():
+        # the hash names candidate occurrences; confirm one exactly
+        if any(np.array_equal(a[o:o + L], b[q:q + L]) for q in np.flatnonzero(hb == ha[o]).tolist()):
+            return o
+    return -1
+
+
+def test_matrix_across_chunks_and_unaligned():
+    """Three noncoding-like sequences of 3M bases with shared mutated
+    segments: 9M ranks span several chunks of the two-level tile scan.
+    Every pair's length equals the single-pair path, off_p is the first
+    offset in a whose length-L window occurs in b, off_q holds the same
+    substring; an sa/lcp pair 4 bytes off 16-byte alignment (the scalar
+    load path) gives identical records."""
+    rng = synth.rng_for(92)
+    k = 3
+    seqs = [synth.noncoding_like(rng, 3_000_000) for _ in range(k)]
+    for i in range(1, k):
+        for _ in range(3):
+            s = int(rng.integers(0, seqs[0].size - 3000))
+            seg = synth.mutate(rng, seqs[0][s:s + int(rng.integers(800, 2500))].copy(), 0.002)
+            p = int(rng.integers(0, seqs[i].size))
+            seqs[i] = np.concatenate([seqs[i][:p], seg, seqs[i][p:]])
+    offs = np.concatenate([[0], np.cumsum([s.size for s in seqs])]).astype(np.int64)
+    d = torch.from_numpy(np.concatenate(seqs)).cuda()
+    r = lor.longest_overlap_region(d, offs)
+    n = r["sa"].numel()
+    say("matrix across chunks", n)
+    assert n > 2 * 4096 * 1024
+    recs = lor.records_to_tuples(lor.lor_overlap_matrix(r["sa"], r["lcp"], offs))
+    sa_buf = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+    lcp_buf = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+    sa_buf[1:].copy_(r["sa"])
+    lcp_buf[1:].copy_(r["lcp"])
+    assert sa_buf[1:].data_ptr() % 16 == 4
+    unaligned = lor.records_to_tuples(lor.lor_overlap_matrix(sa_buf[1:], lcp_buf[1:], offs))
+    assert unaligned == recs
+    for a in range(k):
+        assert recs[a * k + a] == (0, -1, -1, -1, -1)
+        for b in range(k):
+            if a == b:
+                continue
+            L, sp, op, sq, oq = recs[a * k + b]
+            po = np.array([0, seqs[a].size, seqs[a].size + seqs[b].size], np.int64)
+            pd = torch.from_numpy(np.concatenate([seqs[a], seqs[b]])).cuda()
+            assert L == lor.longest_overlap_region(pd, po)["overlap"][0], (a, b)
+            assert L > 500 and (sp, sq) == (a, b)
+            assert np.array_equal(seqs[a][op:op + L], seqs[b][oq:oq + L]), (a, b)
+            assert op == first_shared_window(seqs[a], seqs[b], L), (a, b)
+            assert recs[b * k + a][0] == L
