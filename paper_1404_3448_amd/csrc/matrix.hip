@@ -44,6 +44,7 @@ constexpr uint32_t kMxChunkItems = 4;
 constexpr uint32_t kMxChunk = kMxChunkThreads * kMxChunkItems;   // tiles per chunk (4M ranks)
 constexpr uint32_t kMxChunkWaves = kMxChunkThreads / kWave;
 constexpr int32_t kNoSeq = -1;                     // separator or past the end
+constexpr uint32_t kMxBatch = 8;                   // candidate keys read from LDS together
 
 // Forward state over a run of ranks for one target: the minimum LCP after
 // the run's last target rank (over the whole run if it has none) and that
@@ -115,11 +116,17 @@ __device__ __forceinline__ int32_t seq_of(const int32_t *s_start, uint32_t k, ui
     return (int32_t)lo;
 }
 
-// A lane's ranks: LCP, sequence (kNoSeq for a separator or a rank past n),
-// offset in that sequence and distance to its separator.
+// A lane's ranks, in the forms the per-target loop uses (so that nothing
+// derived from them has to be kept beside them): LCP; 8 x the sequence, the
+// byte offset of its slot in the LDS row of best keys (-8: a separator or a
+// rank past n); ~offset in that sequence, the low word of a candidate key;
+// distance to the sequence's separator.
 struct Lane {
-    int32_t lcp[kMxItems], seq[kMxItems], off[kMxItems], dist[kMxItems];
+    int32_t lcp[kMxItems], seq8[kMxItems];
+    uint32_t noff[kMxItems];
+    int32_t dist[kMxItems];
 };
+constexpr int32_t kNoSeq8 = 8 * kNoSeq;
 
 // vec: sa and lcp are 16-byte aligned, so a full lane reads them as int4.
 __device__ __forceinline__ void load_lane(const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp,
@@ -145,35 +152,43 @@ __device__ __forceinline__ void load_lane(const int32_t *__restrict__ sa, const 
     }
 #pragma unroll
     for (uint32_t i = 0; i < kMxItems; ++i) {
-        L.seq[i] = kNoSeq;
-        L.off[i] = 0;
+        L.seq8[i] = kNoSeq8;
+        L.noff[i] = 0xffffffffu;
         L.dist[i] = 0;
         if (x[i] >= 0) {
             const int32_t j = seq_of(s_start, k, (uint32_t)x[i]);
             const int32_t sep = s_start[j + 1] - 1;
             if (x[i] != sep) {
-                L.seq[i] = j;
-                L.off[i] = x[i] - s_start[j];
+                L.seq8[i] = 8 * j;
+                L.noff[i] = 0xffffffffu - (uint32_t)(x[i] - s_start[j]);
                 L.dist[i] = sep - x[i];
             }
         }
     }
 }
 
-// Folds of a lane's ranks for target t.
-__device__ __forceinline__ Up lane_up(const Lane &L, uint32_t r0, int32_t t) {
-    Up f = up_id();
+// Bit i: rank i of the lane belongs to the target (t8 = 8 x its index).
+__device__ __forceinline__ uint32_t member_mask(const Lane &L, int32_t t8) {
+    uint32_t mask = 0;
 #pragma unroll
-    for (uint32_t i = 0; i < kMxItems; ++i)
-        f = L.seq[i] == t ? Up{INT_MAX, (int32_t)(r0 + i)} : Up{min(f.m, L.lcp[i]), f.last};
-    return f;
+    for (uint32_t i = 0; i < kMxItems; ++i) mask |= (uint32_t)(L.seq8[i] == t8) << i;
+    return mask;
 }
-__device__ __forceinline__ Dn lane_dn(const Lane &L, uint32_t r0, int32_t t) {
-    Dn b = dn_id();
+
+// Folds of a lane's ranks for one target (member mask `mem`): the minimum
+// LCP after the last member (all of them if none) and that rank; the minimum
+// up to and including the first member and that rank.
+__device__ __forceinline__ Up lane_up(const Lane &L, uint32_t r0, uint32_t mem) {
+    int32_t m = INT_MAX;
 #pragma unroll
-    for (int i = (int)kMxItems - 1; i >= 0; --i)
-        b = L.seq[i] == t ? Dn{L.lcp[i], (int32_t)(r0 + i)} : Dn{min(b.m, L.lcp[i]), b.first};
-    return b;
+    for (uint32_t i = 0; i < kMxItems; ++i) m = (mem >> i) & 1u ? INT_MAX : min(m, L.lcp[i]);
+    return Up{m, mem ? (int32_t)(r0 + 31u - __clz(mem)) : -1};
+}
+__device__ __forceinline__ Dn lane_dn(const Lane &L, uint32_t r0, uint32_t mem) {
+    int32_t m = INT_MAX;
+#pragma unroll
+    for (int i = (int)kMxItems - 1; i >= 0; --i) m = (mem >> i) & 1u ? L.lcp[i] : min(m, L.lcp[i]);
+    return Dn{m, mem ? (int32_t)(r0 + __ffs(mem) - 1u) : -1};
 }
 
 __device__ __forceinline__ void load_starts(const int32_t *__restrict__ start, uint32_t k, int32_t *s_start) {
@@ -196,8 +211,9 @@ __global__ __launch_bounds__(kBlock) void k_mx_tiles(const int32_t *__restrict__
     load_lane(sa, lcp, n, r0, s_start, k, vec, L);
     for (uint32_t t = 0; t < k; ++t) {
         const uint32_t buf = t & 1u;   // a wave may write target t + 1 while thread 0 reads target t
-        const Up fu = wave_incl_up(lane_up(L, r0, (int32_t)t));
-        const Dn fd = wave_incl_dn(lane_dn(L, r0, (int32_t)t));
+        const uint32_t mem = member_mask(L, 8 * (int32_t)t);
+        const Up fu = wave_incl_up(lane_up(L, r0, mem));
+        const Dn fd = wave_incl_dn(lane_dn(L, r0, mem));
         if (lane == kWave - 1) s_wu[buf][w] = fu;
         if (lane == 0) s_wd[buf][w] = fd;
         __syncthreads();
@@ -277,15 +293,11 @@ __global__ __launch_bounds__(kMxChunkThreads) void k_mx_chunks(Up *__restrict__ 
     }
 }
 
-__device__ __forceinline__ unsigned long long cand_key(int32_t m, int32_t off) {
-    return ((unsigned long long)(uint32_t)m << 32) | (0xffffffffu - (uint32_t)off);
-}
-
 // EMIT 0: fold every credited match of a rank of sequence j != t with target
 // t into best[j * k + t] = max(m << 32 | ~offset). EMIT 1: the rank holding
 // its pair's best key writes the record.
 template <int EMIT>
-__global__ __launch_bounds__(kBlock) void k_mx_ranks(const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_mx_ranks(const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp,
                                                      uint32_t n, const int32_t *__restrict__ start, uint32_t k,
                                                      bool vec, uint32_t tiles, uint32_t chunks,
                                                      const Up *__restrict__ tu,
@@ -296,6 +308,13 @@ __global__ __launch_bounds__(kBlock) void k_mx_ranks(const int32_t *__restrict__
     __shared__ unsigned long long s_best[kMaxSeqs];   // column t of best, this workgroup's copy
     __shared__ Up s_wu[kMxWaves];
     __shared__ Dn s_wd[kMxWaves];
+    // EMIT 1: the ranks holding a best key queue {j, neighbour, m, offset};
+    // the records are written after the target's walk. A key belongs to one
+    // rank, so a target queues at most k entries. Indexed by target parity:
+    // a queue is cleared two targets after it was read.
+    __shared__ int4 s_q[2][kMaxSeqs];
+    __shared__ uint32_t s_nq[2];
+    if (threadIdx.x < 2) s_nq[threadIdx.x] = 0;
     load_starts(start, k, s_start);
     const uint32_t tile = blockIdx.x, w = threadIdx.x / kWave, lane = dev::lane_id();
     const uint32_t r0 = tile * kMxTile + threadIdx.x * kMxItems;
@@ -304,12 +323,16 @@ __global__ __launch_bounds__(kBlock) void k_mx_ranks(const int32_t *__restrict__
     load_lane(sa, lcp, n, r0, s_start, k, vec, L);
     for (uint32_t t = 0; t < k; ++t) {
         const int32_t ti = (int32_t)t;
+        const uint32_t buf = t & 1u;
+        if (EMIT == 1 && threadIdx.x == 0 && t >= 1) s_nq[buf ^ 1u] = 0;   // read before the last barrier
         // carries of everything before and after the tile (two-level scan)
         const Up carry_u = up_comb(cu[(size_t)t * chunks + c], tu[(size_t)t * tiles + tile]);
         const Dn carry_d = dn_comb(td[(size_t)t * tiles + tile], cd[(size_t)t * chunks + c]);
         for (uint32_t j = threadIdx.x; j < k; j += kBlock) s_best[j] = j == t ? 0ull : best[(size_t)j * k + t];
-        const Up iu = wave_incl_up(lane_up(L, r0, ti));
-        const Dn id = wave_incl_dn(lane_dn(L, r0, ti));
+        const int32_t t8 = 8 * ti;
+        const uint32_t members = member_mask(L, t8);
+        const Up iu = wave_incl_up(lane_up(L, r0, members));
+        const Dn id = wave_incl_dn(lane_dn(L, r0, members));
         if (lane == kWave - 1) s_wu[w] = iu;
         if (lane == 0) s_wd[w] = id;
         __syncthreads();
@@ -319,38 +342,85 @@ __global__ __launch_bounds__(kBlock) void k_mx_ranks(const int32_t *__restrict__
         Dn bs = carry_d;
         for (uint32_t v = kMxWaves - 1; v > w; --v) bs = dn_comb(s_wd[v], bs);
         bs = dn_comb(wave_excl_dn(id), bs);
-        // forward walk: the match above every rank
-        int32_t up_m[kMxItems], up_at[kMxItems];
+        // Walks. With no target rank yet seen the running minimum starts at 0
+        // (the match is 0 then) and a member resets it, so the running value
+        // is the match itself. Forward: the match above every rank.
+        const int32_t in_last = fs.last, in_first = bs.first;
+        int32_t fm = fs.last >= 0 ? fs.m : 0;
+        int32_t up_m[kMxItems];
 #pragma unroll
         for (uint32_t i = 0; i < kMxItems; ++i) {
-            fs = L.seq[i] == ti ? Up{INT_MAX, (int32_t)(r0 + i)} : Up{min(fs.m, L.lcp[i]), fs.last};
-            up_m[i] = fs.last >= 0 ? fs.m : 0;
-            up_at[i] = fs.last;
+            fm = (members >> i) & 1u ? INT_MAX : min(fm, L.lcp[i]);
+            up_m[i] = fm;
         }
-        // backward walk: the match below, then the candidate
+        // backward: the match below; the credited length replaces the match
+        // above in up_m, and bit i of from_up says the rank above gave it (it
+        // wins a tie)
+        int32_t bm = bs.first >= 0 ? bs.m : 0;
+        uint32_t from_up = 0;
 #pragma unroll
         for (int i = (int)kMxItems - 1; i >= 0; --i) {
-            const int32_t down = bs.first >= 0 ? bs.m : 0, down_at = bs.first;
-            bs = L.seq[i] == ti ? Dn{L.lcp[i], (int32_t)(r0 + i)} : Dn{min(bs.m, L.lcp[i]), bs.first};
-            const int32_t j = L.seq[i];
-            if (j == kNoSeq || j == ti) continue;
-            const int32_t m = min(max(up_m[i], down), L.dist[i]);
-            if (m <= 0) continue;
-            const unsigned long long key = cand_key(m, L.off[i]);
-            if (EMIT == 0) {
-                if (key > s_best[j]) atomicMax(&s_best[j], key);
-            } else if (key == s_best[j]) {
-                const int32_t at = up_m[i] >= down ? up_at[i] : down_at;   // the neighbour that gave m
-                lor_overlap rec;
-                rec.length = m;
-                rec.seq_p = j;
-                rec.off_p = L.off[i];
-                rec.seq_q = ti;
-                rec.off_q = (at >= 0 && (uint32_t)at < n) ? sa[at] - s_start[t] : -1;
-                out[(size_t)j * k + t] = rec;
+            const int32_t down = bm;
+            bm = (members >> i) & 1u ? L.lcp[i] : min(bm, L.lcp[i]);
+            const bool other = L.seq8[i] != kNoSeq8 && L.seq8[i] != t8;
+            from_up |= (uint32_t)(up_m[i] >= down) << i;
+            up_m[i] = other ? min(max(up_m[i], down), L.dist[i]) : 0;
+        }
+        // candidates, kMxBatch at a time: the best keys are read before any
+        // compare, so their LDS latency overlaps; only the rare insert (or
+        // queue) is a branch
+        const char *s_row = reinterpret_cast<const char *>(s_best);
+        uint32_t hit = 0;
+#pragma unroll
+        for (uint32_t c0 = 0; c0 < kMxItems; c0 += kMxBatch) {
+            unsigned long long cur[kMxBatch];
+#pragma unroll
+            for (uint32_t u = 0; u < kMxBatch; ++u)
+                cur[u] = *reinterpret_cast<const unsigned long long *>(s_row + (up_m[c0 + u] > 0 ? L.seq8[c0 + u] : 0));
+#pragma unroll
+            for (uint32_t u = 0; u < kMxBatch; ++u) {
+                const uint32_t i = c0 + u;
+                const int32_t m = up_m[i];
+                const unsigned long long key = ((unsigned long long)(uint32_t)m << 32) | L.noff[i];
+                if (EMIT == 0) {
+                    if (m > 0 && key > cur[u])
+                        atomicMax(reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(s_best) + L.seq8[i]),
+                                  key);
+                } else {
+                    hit |= (uint32_t)(m > 0 && key == cur[u]) << i;
+                }
             }
         }
+        // EMIT 1: ranks holding their pair's best key (rare). The key gives
+        // m and the offset, the rank's suffix its sequence; the neighbour is
+        // the lane's last member at or before it (else the one carried in)
+        // or its first member after it (else the one carried in).
+        while (EMIT == 1 && hit) {
+            const uint32_t i = __ffs(hit) - 1u;
+            hit &= hit - 1u;
+            const int32_t j = seq_of(s_start, k, (uint32_t)sa[r0 + i]);
+            const unsigned long long key = s_best[j];
+            const uint32_t upto = members & ((2u << i) - 1u), after = members & ~((2u << i) - 1u);
+            const int32_t up_at = upto ? (int32_t)(r0 + 31u - __clz(upto)) : in_last;
+            const int32_t down_at = after ? (int32_t)(r0 + __ffs(after) - 1u) : in_first;
+            const int32_t at = (from_up >> i) & 1u ? up_at : down_at;   // the neighbour that gave m
+            const uint32_t q = atomicAdd(&s_nq[buf], 1u);
+            if (q < kMaxSeqs) s_q[buf][q] = make_int4(j, at, (int32_t)(key >> 32), (int32_t)(0xffffffffu - (uint32_t)key));
+        }
         __syncthreads();
+        if (EMIT == 1) {
+            const uint32_t nq = min(s_nq[buf], (uint32_t)kMaxSeqs);
+            for (uint32_t e = threadIdx.x; e < nq; e += kBlock) {
+                const int4 q = s_q[buf][e];
+                lor_overlap rec;
+                rec.length = q.z;
+                rec.seq_p = q.x;
+                rec.off_p = q.w;
+                rec.seq_q = ti;
+                rec.off_q = (q.y >= 0 && (uint32_t)q.y < n) ? sa[q.y] - s_start[t] : -1;
+                out[(size_t)q.x * k + t] = rec;
+            }
+        }
         if (EMIT == 0)
             // same thread-to-slot map as the copy-in above, so the next
             // target's copy-in needs no barrier of its own
