@@ -40,13 +40,39 @@ __device__ __forceinline__ uint32_t seq_at(const int32_t *__restrict__ start, ui
     return lo;
 }
 
+// Sequence lookups go through buckets of 2^kRqBucketShift positions:
+// tab[b] = the sequence holding position min(b << shift, N - 1), b = 0..nb
+// with nb = ceil(N / 2^shift). Sequences only grow with the position, so the
+// one holding x lies in [tab[x >> shift], tab[(x >> shift) + 1]]: a search
+// of a few starts (queries are at least tens of bases) instead of all of
+// them.
+constexpr uint32_t kRqBucketShift = 6;
+
+__global__ __launch_bounds__(kBlock) void k_rq_buckets(const int32_t *__restrict__ start, uint32_t S, uint32_t N,
+                                                       uint32_t nb, int32_t *__restrict__ tab) {
+    for (uint32_t b = blockIdx.x * kBlock + threadIdx.x; b <= nb; b += gridDim.x * kBlock)
+        tab[b] = (int32_t)seq_at(start, S, min((uint64_t)b << kRqBucketShift, (uint64_t)N - 1));
+}
+
+// Largest j with start[j] <= x, for x < N.
+__device__ __forceinline__ uint32_t seq_fast(const int32_t *__restrict__ start, const int32_t *__restrict__ tab,
+                                             uint32_t x) {
+    const uint32_t b = x >> kRqBucketShift;
+    uint32_t lo = (uint32_t)tab[b], hi = (uint32_t)tab[b + 1];
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if ((uint32_t)start[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // start[j] = joined start of sequence j (0 = reference), start[S] = N.
 __global__ __launch_bounds__(kBlock) void k_rq_join(const uint8_t *__restrict__ seqs, const int32_t *__restrict__ start,
-                                                    uint32_t S, uint32_t N, uint8_t *__restrict__ out,
-                                                    uint32_t *__restrict__ err) {
+                                                    const int32_t *__restrict__ tab, uint32_t N,
+                                                    uint8_t *__restrict__ out, uint32_t *__restrict__ err) {
     uint32_t bad = 0;
     for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < N; p += gridDim.x * kBlock) {
-        const uint32_t j = seq_at(start, S, p);
+        const uint32_t j = seq_fast(start, tab, p);
         uint32_t c;
         if (p + 1 == (uint32_t)start[j + 1]) {
             c = 4u;
@@ -198,7 +224,8 @@ __global__ __launch_bounds__(kRqScanThreads) void k_rq_tile_scan(Fwd *__restrict
 // writes the record.
 __global__ __launch_bounds__(kBlock) void k_rq_ranks(const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp,
                                                      uint32_t n, Target tg, const int32_t *__restrict__ start,
-                                                     uint32_t S, const Fwd *__restrict__ pre,
+                                                     const int32_t *__restrict__ tab, uint32_t S,
+                                                     const Fwd *__restrict__ pre,
                                                      const Bwd *__restrict__ post, int emit, uint32_t stride,
                                                      int32_t base, unsigned long long *__restrict__ best,
                                                      lor_overlap *__restrict__ out) {
@@ -232,10 +259,12 @@ __global__ __launch_bounds__(kBlock) void k_rq_ranks(const int32_t *__restrict__
         bs = b_comb(b_elem(it[k], r), bs);
         const uint32_t x = (uint32_t)it[k].sa;
         if (x >= tg.lo && x <= tg.hi) continue;   // target suffix or its separator
-        const uint32_t j = seq_at(start, S, x);
+        const int32_t mx = max(up[k], down);
+        if (mx <= 0) continue;
+        const uint32_t j = seq_fast(start, tab, x);
         if (j >= S || j == tg.seq) continue;
         const uint32_t d = (uint32_t)start[j + 1] - 1u - x;   // distance to its own separator
-        const int32_t m = min(max(up[k], down), (int32_t)d);
+        const int32_t m = min(mx, (int32_t)d);
         if (m <= 0) continue;
         const uint32_t off = x - (uint32_t)start[j];
         const unsigned long long key = ((unsigned long long)(uint32_t)m << 32) | (0xffffffffu - off);
@@ -273,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_rq_init(uint32_t Q, unsigned long lo
 
 struct RqLayout {
     uint8_t *text;
-    int32_t *sa, *lcp, *start;
+    int32_t *sa, *lcp, *start, *tab;
     unsigned long long *best;
     Fwd *tf;
     Bwd *tb;
@@ -285,6 +314,7 @@ lor_status rq_carve(Arena &ar, uint64_t N, uint32_t S, RqLayout *L) {
     LOR_TAKE(ar, int32_t, N, L->sa);
     LOR_TAKE(ar, int32_t, N, L->lcp);
     LOR_TAKE(ar, int32_t, (size_t)S + 1, L->start);
+    LOR_TAKE(ar, int32_t, (size_t)div_up(N ? N : 1, 1u << kRqBucketShift) + 1, L->tab);
     LOR_TAKE(ar, unsigned long long, S, L->best);
     LOR_TAKE(ar, Fwd, tiles, L->tf);
     LOR_TAKE(ar, Bwd, tiles, L->tb);
@@ -294,7 +324,7 @@ lor_status rq_carve(Arena &ar, uint64_t N, uint32_t S, RqLayout *L) {
 // Matches of every other sequence's suffixes with one target sequence:
 // tile states, their scan, then the two per-rank passes.
 lor_status target_scan(const int32_t *sa, const int32_t *lcp, uint32_t n, Target tg, const int32_t *start,
-                       uint32_t S, uint32_t stride, int32_t base, Fwd *tf, Bwd *tb, unsigned long long *best,
+                       const int32_t *tab, uint32_t S, uint32_t stride, int32_t base, Fwd *tf, Bwd *tb, unsigned long long *best,
                        lor_overlap *out, hipStream_t s) {
     const uint32_t tiles = div_up(n, kRqTile);
     LOR_LAUNCH("k_rq_tiles", 8.0 * n, s,
@@ -303,7 +333,7 @@ lor_status target_scan(const int32_t *sa, const int32_t *lcp, uint32_t n, Target
                hipLaunchKernelGGL(k_rq_tile_scan, dim3(1), dim3(kRqScanThreads), 0, s, tf, tb, tiles));
     for (int emit = 0; emit < 2; ++emit)
         LOR_LAUNCH("k_rq_ranks", 8.0 * n, s,
-                   hipLaunchKernelGGL(k_rq_ranks, dim3(tiles), dim3(kBlock), 0, s, sa, lcp, n, tg, start, S, tf, tb,
+                   hipLaunchKernelGGL(k_rq_ranks, dim3(tiles), dim3(kBlock), 0, s, sa, lcp, n, tg, start, tab, S, tf, tb,
                                       emit, stride, base, best, out));
     return LOR_OK;
 }
@@ -347,16 +377,20 @@ lor_status refq_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t Q,
     LOR_TRY(zero_words(hdr, 16, s));
     LOR_LAUNCH("k_rq_init", 40.0 * Q, s,
                hipLaunchKernelGGL(k_rq_init, dim3(grid_for(Q)), dim3(kBlock), 0, s, Q, L.best, out));
+    const uint32_t nb = div_up(N, 1u << kRqBucketShift);
+    LOR_LAUNCH("k_rq_buckets", 4.0 * (nb + 1), s,
+               hipLaunchKernelGGL(k_rq_buckets, dim3(grid_for(nb + 1)), dim3(kBlock), 0, s, L.start, S, (uint32_t)N,
+                                  nb, L.tab));
     LOR_LAUNCH("k_rq_join", 2.0 * N, s,
-               hipLaunchKernelGGL(k_rq_join, dim3(grid_for(N)), dim3(kBlock), 0, s, seqs, L.start, S, (uint32_t)N,
-                                  L.text, hdr));
+               hipLaunchKernelGGL(k_rq_join, dim3(grid_for(N)), dim3(kBlock), 0, s, seqs, L.start, L.tab,
+                                  (uint32_t)N, L.text, hdr));
     // symbols byte + 1: bases 1..4, separator 5
     LOR_TRY(dc3_u8(L.text, (uint32_t)N, 5u, L.sa, ar, hdr, s));
     ar.release(phase);
     LOR_TRY(lcp_build(L.text, (uint32_t)N, L.sa, L.lcp, nullptr, ar, s));
     ar.release(phase);
-    LOR_TRY(target_scan(L.sa, L.lcp, (uint32_t)N, Target{0u, ref_len, 0u}, L.start, S, 1u, -1, L.tf, L.tb, L.best,
-                        out, s));
+    LOR_TRY(target_scan(L.sa, L.lcp, (uint32_t)N, Target{0u, ref_len, 0u}, L.start, L.tab, S, 1u, -1, L.tf, L.tb,
+                        L.best, out, s));
     LOR_HIP(hipStreamSynchronize(s));   // the host table must outlive its copy
     return LOR_OK;
 }

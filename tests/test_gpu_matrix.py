@@ -71,6 +71,25 @@ def test_matrix_random(seed):
     check(seqs)
 
 
+def test_matrix_max_sequences():
+    """251 sequences (the most one joined text holds): every row of best keys,
+    start table and record queue in LDS is full, and some sequences are empty
+    or a single base."""
+    rng = np.random.default_rng(1300)
+    k = 251
+    seqs = [rng.integers(0, int(rng.integers(1, 5)), size=int(rng.integers(0, 24)), dtype=np.uint8)
+            for _ in range(k)]
+    for _ in range(60):
+        a, b = rng.integers(0, k, size=2)
+        if a != b and seqs[a].size > 6:
+            s = int(rng.integers(0, seqs[a].size - 4))
+            p = int(rng.integers(0, seqs[b].size + 1))
+            seqs[b] = np.concatenate([seqs[b][:p], seqs[a][s:s + 5], seqs[b][p:]])
+    seqs[7] = np.zeros(0, np.uint8)
+    seqs[8] = np.array([2], np.uint8)
+    check(seqs)
+
+
 def test_matrix_noncoding():
     rng = synth.rng_for(91)
     seqs = [synth.noncoding_like(rng, int(rng.integers(1000, 20000))) for _ in range(8)]
