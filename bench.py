@@ -361,9 +361,22 @@ def main():
         torch.cuda.synchronize()
         log(f"warmup {i}: {1e3 * (time.perf_counter() - t):.1f} ms, overlap {ov}")
 
+    # Per-kernel breakdown: one more untimed step with events around every
+    # launch. The timed steps then carry events only around the launches of
+    # the dominant kernel, whose live average duration gives the roofline.
+    kernels = {}
+    dom_live = None
     if not args.no_kernel_timing:
+        lor.lor_timing_only(None)
         lor.lor_timing_reset()
         lor.lor_timing_enable(True)
+        step()
+        torch.cuda.synchronize()
+        kernels = lor.lor_timing_read()
+        dom_live = max(kernels.items(), key=lambda kv: kv[1]["ms"])[0] if kernels else None
+        log(f"kernel breakdown step done; timing {dom_live} live")
+        lor.lor_timing_reset()
+        lor.lor_timing_only(dom_live)
     stage_ms = {k: 0.0 for k in names}
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -376,10 +389,11 @@ def main():
         log(f"step {i}: {ev[0].elapsed_time(ev[5]):.1f} ms")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    kernels = {}
+    live = {}
     if not args.no_kernel_timing:
-        kernels = lor.lor_timing_read()
+        live = lor.lor_timing_read()
         lor.lor_timing_enable(False)
+        lor.lor_timing_only(None)
 
     ms_per_step = 1e3 * elapsed / args.steps
     value = N / (elapsed / args.steps) / 1e6
@@ -388,16 +402,16 @@ def main():
 
     roofline = None
     kern_out = {}
-    for name, k in sorted(kernels.items(), key=lambda kv: -kv[1]["ms"]):
+    for name, k in sorted(kernels.items(), key=lambda kv: -kv[1]["ms"]):   # one step's worth
         gbs = k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0
-        kern_out[name] = {"launches_per_step": k["launches"] / args.steps, "ms_per_step": round(k["ms"] / args.steps, 3),
+        kern_out[name] = {"launches_per_step": k["launches"], "ms_per_step": round(k["ms"], 3),
                           "alg_GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
         # HBM bytes the counters measured for this kernel (1G workload, same sources) over the same time
         per_launch = committed_traffic(name) if args.workload == "1g" and k["ms"] > 0 else None
         if per_launch is not None:
             kern_out[name]["hbm_GBps"] = round(per_launch * k["launches"] / (k["ms"] * 1e-3) / 1e9, 1)
-    if kernels:
-        dom_name, dom = max(kernels.items(), key=lambda kv: kv[1]["ms"])
+    if live.get(dom_live):
+        dom_name, dom = dom_live, live[dom_live]   # events over the timed steps
         achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
         traffic = committed_traffic(dom_name) if args.workload == "1g" else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

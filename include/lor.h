@@ -310,8 +310,10 @@ lor_status lor_plan_set(const lor_plan *plan);
 /* --------------------------------------------------------- kernel timing
  * Optional per-kernel timing with HIP events recorded on the launch stream
  * around every launch of the named kernel families. Disabled by default.
- * lor_timing_read fills up to `cap` records and returns how many families
- * were timed; it synchronises each pending event. Not thread-safe. */
+ * lor_timing_only(family) limits the events to one family (NULL or "": all
+ * families); the string is copied. lor_timing_read fills up to `cap` records
+ * and returns how many families were timed; it synchronises each pending
+ * event. Not thread-safe. */
 typedef struct {
     char name[32];          /* kernel family */
     int64_t launches;
@@ -320,6 +322,7 @@ typedef struct {
 } lor_timing;
 
 void lor_timing_enable(int32_t on);
+void lor_timing_only(const char *family);
 void lor_timing_reset(void);
 int32_t lor_timing_read(lor_timing *out, int32_t cap);
 

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <initializer_list>
+#include <string>
 #include <vector>
 
 #include "lor_internal.hpp"
@@ -28,6 +29,7 @@ struct FamilyStat {
 };
 constexpr int kMaxFamilies = 96;
 bool g_timing = false;
+std::string g_timing_only;   // empty: every family
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_event_pool;
 FamilyStat g_stats[kMaxFamilies];
@@ -105,6 +107,7 @@ bool trace_on() {
 }
 
 int timing_begin(hipStream_t s, const char *kernel, double bytes) {
+    if (!g_timing_only.empty() && g_timing_only != kernel) return -1;
     const int f = family_of(kernel);
     if (g_pending.size() > 100000) drain_pending();
     Pending p;
@@ -754,6 +757,8 @@ lor_status lor_plan_set(const lor_plan *p) {
 }
 
 void lor_timing_enable(int32_t on) { g_timing = on != 0; }
+
+void lor_timing_only(const char *family) { g_timing_only = family ? family : ""; }
 
 void lor_timing_reset(void) {
     drain_pending();

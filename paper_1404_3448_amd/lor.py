@@ -111,6 +111,7 @@ def lib():
         "lor_plan_get": ([ctypes.POINTER(lor_plan)], None),
         "lor_plan_set": ([ctypes.POINTER(lor_plan)], I32),
         "lor_timing_enable": ([I32], None),
+        "lor_timing_only": ([ctypes.c_char_p], None),
         "lor_timing_reset": ([], None),
         "lor_timing_read": ([ctypes.POINTER(lor_timing), I32], I32),
     }
@@ -544,6 +545,11 @@ def make_plan(**fields) -> lor_plan:
 
 def lor_timing_enable(on: bool = True):
     lib().lor_timing_enable(1 if on else 0)
+
+
+def lor_timing_only(family=None):
+    """Limit event timing to one kernel family (None: every family)."""
+    lib().lor_timing_only(family.encode() if family else None)
 
 
 def lor_timing_reset():

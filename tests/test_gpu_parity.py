@@ -400,3 +400,32 @@ def test_rmq_compact_equals_oracle_and_full_table(n, values):
     assert np.array_equal(mc, mf) and np.array_equal(ac, af)
     for k in range(0, lo.size, 7):
         assert (mc[k], ac[k]) == oracle.range_min(lcp_h, lo[k], hi[k])
+
+
+def test_kernel_timing_registry_and_filter():
+    """Event timing counts every launch of every family; limited to one
+    family it records that family alone, with the same launch count."""
+    rng = np.random.default_rng(8)
+    seqs = [rng.integers(0, 4, size=5000, dtype=np.uint8) for _ in range(3)]
+    offs = np.concatenate([[0], np.cumsum([s.size for s in seqs])]).astype(np.int64)
+    d = torch.from_numpy(np.concatenate(seqs)).cuda()
+    try:
+        lor.lor_timing_only(None)
+        lor.lor_timing_reset()
+        lor.lor_timing_enable(True)
+        lor.longest_overlap_region(d, offs)
+        torch.cuda.synchronize()
+        everything = lor.lor_timing_read()
+        assert {"k_join", "k_radix_scatter", "k_merge", "k_plcp"} <= set(everything)
+        assert all(v["launches"] > 0 and v["ms"] > 0 for v in everything.values())
+        lor.lor_timing_reset()
+        lor.lor_timing_only("k_radix_scatter")
+        lor.longest_overlap_region(d, offs)
+        torch.cuda.synchronize()
+        one = lor.lor_timing_read()
+        assert set(one) == {"k_radix_scatter"}
+        assert one["k_radix_scatter"]["launches"] == everything["k_radix_scatter"]["launches"]
+    finally:
+        lor.lor_timing_enable(False)
+        lor.lor_timing_only(None)
+        lor.lor_timing_reset()
