@@ -109,17 +109,23 @@ uint32_t scan_groups(uint32_t items) {
 
 // ---------------------------------------------------------------- join
 
+// A thread writes kJoinBytes consecutive output bytes. When they are all
+// bases of one sequence (almost always), they are the input shifted by the
+// sequence index: three aligned 8-byte loads and a funnel shift, the base
+// check on whole words. Windows that hold a separator, or sit near either
+// end of the input, go byte by byte.
+constexpr uint32_t kJoinBytes = 16;
+
 __global__ __launch_bounds__(kBlock) void k_join(const uint8_t *__restrict__ seqs, SeqStarts st,
-                                                 uint32_t N, uint8_t *__restrict__ out,
+                                                 uint32_t N, uint32_t total, uint8_t *__restrict__ out,
                                                  uint32_t *__restrict__ err) {
     __shared__ int32_t s_start[kMaxSeqs + 1];
     for (int i = threadIdx.x; i <= st.k; i += kBlock) s_start[i] = st.start[i];
     __syncthreads();
     const int k = st.k;
     uint32_t bad = 0;
-    const uint32_t stride = gridDim.x * kBlock * 4u;
-    for (uint32_t p0 = (blockIdx.x * kBlock + threadIdx.x) * 4u; p0 < N; p0 += stride) {
-        uint32_t word = 0;
+    const uint32_t stride = gridDim.x * kBlock * kJoinBytes;
+    for (uint32_t p0 = (blockIdx.x * kBlock + threadIdx.x) * kJoinBytes; p0 < N; p0 += stride) {
         int j = 0;
         {   // sequence containing p0: largest j with start[j] <= p0
             int lo = 0, hi = k - 1;
@@ -129,23 +135,44 @@ __global__ __launch_bounds__(kBlock) void k_join(const uint8_t *__restrict__ seq
             }
             j = lo;
         }
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t p = p0 + u;
-            if (p >= N) break;
-            while ((uint32_t)s_start[j + 1] <= p) ++j;
-            uint32_t byte;
-            if (p == (uint32_t)s_start[j + 1] - 1u) {
-                byte = 4u + (uint32_t)j;
-            } else {
-                byte = seqs[p - (uint32_t)j];
-                bad |= byte > 3u;
-            }
-            word |= byte << (8 * u);
+        uint32_t *o = reinterpret_cast<uint32_t *>(out + p0);   // p0 is a multiple of 16, out of 4
+        const uint32_t src = p0 - (uint32_t)j;
+        if (p0 + kJoinBytes < (uint32_t)s_start[j + 1] && src >= 8u && src + 24u <= total) {
+            const uintptr_t addr = reinterpret_cast<uintptr_t>(seqs + src);
+            const uint64_t *w = reinterpret_cast<const uint64_t *>(addr & ~(uintptr_t)7);
+            const uint32_t sh = (uint32_t)(addr & 7u) * 8u;
+            const uint64_t w0 = w[0], w1 = w[1], w2 = w[2];
+            const uint64_t lo = sh ? (w0 >> sh) | (w1 << (64u - sh)) : w0;
+            const uint64_t hi = sh ? (w1 >> sh) | (w2 << (64u - sh)) : w1;
+            bad |= ((lo | hi) & 0xfcfcfcfcfcfcfcfcull) != 0;
+            o[0] = (uint32_t)lo;
+            o[1] = (uint32_t)(lo >> 32);
+            o[2] = (uint32_t)hi;
+            o[3] = (uint32_t)(hi >> 32);
+            continue;
         }
-        if (p0 + 4 <= N) {
-            *reinterpret_cast<uint32_t *>(out + p0) = word;   // p0 is a multiple of 4
-        } else {
-            for (uint32_t u = 0; p0 + u < N; ++u) out[p0 + u] = (uint8_t)(word >> (8 * u));
+        for (uint32_t q = 0; q < kJoinBytes / 4; ++q) {
+            uint32_t word = 0;
+            for (uint32_t u = 0; u < 4; ++u) {
+                const uint32_t p = p0 + 4 * q + u;
+                if (p >= N) break;
+                while ((uint32_t)s_start[j + 1] <= p) ++j;
+                uint32_t byte;
+                if (p == (uint32_t)s_start[j + 1] - 1u) {
+                    byte = 4u + (uint32_t)j;
+                } else {
+                    byte = seqs[p - (uint32_t)j];
+                    bad |= byte > 3u;
+                }
+                word |= byte << (8 * u);
+            }
+            const uint32_t pw = p0 + 4 * q;
+            if (pw >= N) break;
+            if (pw + 4 <= N) {
+                o[q] = word;
+            } else {
+                for (uint32_t u = 0; pw + u < N; ++u) out[pw + u] = (uint8_t)(word >> (8 * u));
+            }
         }
     }
     if (__any(bad) && dev::lane_id() == 0) atomicOr(err, 1u);
@@ -1147,8 +1174,8 @@ lor_status join_text(const uint8_t *seqs, const int64_t *offsets, int32_t k, uin
     const uint32_t N = (uint32_t)(offsets[k] + k);
     if (N == 0) return LOR_OK;
     LOR_LAUNCH("k_join", 2.0 * N, s,
-               hipLaunchKernelGGL(k_join, dim3(grid_for(div_up(N, 4))), dim3(kBlock), 0, s, seqs, st, N, out,
-                                  err_word));
+               hipLaunchKernelGGL(k_join, dim3(grid_for(div_up(N, kJoinBytes))), dim3(kBlock), 0, s, seqs, st, N,
+                                  (uint32_t)offsets[k], out, err_word));
     return LOR_OK;
 }
 

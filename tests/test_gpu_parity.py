@@ -196,6 +196,30 @@ def test_build_sa_lcp_many_sequences(seed):
     assert ov == oracle.overlap(want_sa, oracle.lcp(want_joined, want_sa), offs)
 
 
+@pytest.mark.parametrize("shift", [0, 1, 3, 7, 13])
+def test_join_from_misaligned_bases_and_bad_base_inside(shift):
+    """The bases start `shift` bytes into their buffer, so the join's word
+    loads meet every byte alignment; a bad base deep inside a long sequence
+    (a window copied whole) is still reported."""
+    rng = np.random.default_rng(40 + shift)
+    seqs = [rng.integers(0, 4, size=n, dtype=np.uint8) for n in (5003, 17, 0, 4096, 2999)]
+    offs = np.concatenate([[0], np.cumsum([s.size for s in seqs])]).astype(np.int64)
+    flat = np.concatenate(seqs)
+    buf = torch.zeros(flat.size + shift + 16, dtype=torch.uint8, device="cuda")
+    buf[shift:shift + flat.size].copy_(torch.from_numpy(flat))
+    d = buf[shift:shift + flat.size]
+    sa, joined = lor.lor_build_sa(d, offs)
+    want = oracle.join(flat, offs)
+    assert np.array_equal(host(joined), want)
+    assert np.array_equal(host(sa), oracle.suffix_array(want))
+    bad = flat.copy()
+    bad[2500] = 7
+    buf[shift:shift + flat.size].copy_(torch.from_numpy(bad))
+    with pytest.raises(lor.LorError) as e:
+        lor.lor_build_sa(d, offs)
+    assert e.value.status == lor.LOR_EALPHABET
+
+
 def test_build_sa_rejects_bad_base():
     d, offs = build([[0, 1, 2], [3, 7, 1]])
     with pytest.raises(lor.LorError) as e:
