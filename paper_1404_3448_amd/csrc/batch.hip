@@ -84,11 +84,20 @@ __device__ __forceinline__ uint32_t pair_at(const PairWin &w, const int32_t *s_s
 // src[2p], src[2p+1] = offsets of A_p and B_p in the separator-free input.
 constexpr uint32_t kJoinTile = kBlock * 16;   // positions per workgroup
 
+// A thread writes groups of kJoinGroup consecutive positions (groups of
+// neighbouring threads are neighbours). A group inside one sequence of a pair
+// is its bases shifted: aligned 8-byte loads and a funnel shift, the base
+// check on the whole word, one 16-byte store of codes 8p + 1 + base. Other
+// groups (a separator, a pair boundary, either end of the input) go position
+// by position.
+constexpr uint32_t kJoinGroup = 8;
+
 __global__ __launch_bounds__(kBlock) void k_join_pairs(const uint8_t *__restrict__ seqs,
                                                        const int32_t *__restrict__ start,
                                                        const int32_t *__restrict__ alen,
                                                        const int64_t *__restrict__ src, uint32_t P, uint32_t N,
-                                                       uint16_t *__restrict__ out, uint32_t *__restrict__ err) {
+                                                       uint64_t total, uint16_t *__restrict__ out,
+                                                       uint32_t *__restrict__ err) {
     __shared__ int32_t s_start[kPairWin + 1];
     __shared__ int32_t s_alen[kPairWin];
     __shared__ uint32_t s_sh[2];
@@ -97,28 +106,53 @@ __global__ __launch_bounds__(kBlock) void k_join_pairs(const uint8_t *__restrict
     const uint32_t cnt = min(kJoinTile, N - base);
     const PairWin w = pair_window(start, alen, P, base, base + cnt - 1, s_start, s_alen, s_sh);
     uint32_t bad = 0, cur = 0;
-    for (uint32_t j = threadIdx.x; j < cnt; j += kBlock) {
-        const uint32_t i = base + j;
-        const uint32_t q = pair_at(w, s_start, start, P, i, cur), p = w.lo + q;
-        const uint32_t s0 = w.lds ? (uint32_t)s_start[q] : (uint32_t)start[p];
-        const uint32_t s1 = w.lds ? (uint32_t)s_start[q + 1] : (uint32_t)start[p + 1];
-        const uint32_t a = w.lds ? (uint32_t)s_alen[q] : (uint32_t)alen[p];
-        const uint32_t o = i - s0, plen = s1 - s0;
-        uint32_t code;
-        if (o < a) {
-            code = seqs[src[2 * p] + o];
-            bad |= code > 3u;
-            code += 1u;
-        } else if (o == a) {
-            code = 5u;
-        } else if (o + 1 < plen) {
-            code = seqs[src[2 * p + 1] + (o - a - 1)];
-            bad |= code > 3u;
-            code += 1u;
-        } else {
-            code = 6u;
+    for (uint32_t g0 = threadIdx.x * kJoinGroup; g0 < cnt; g0 += kBlock * kJoinGroup) {
+        const uint32_t i0 = base + g0;
+        const uint32_t q0 = pair_at(w, s_start, start, P, i0, cur), p0 = w.lo + q0;
+        const uint32_t s0 = w.lds ? (uint32_t)s_start[q0] : (uint32_t)start[p0];
+        const uint32_t s1 = w.lds ? (uint32_t)s_start[q0 + 1] : (uint32_t)start[p0 + 1];
+        const uint32_t a0 = w.lds ? (uint32_t)s_alen[q0] : (uint32_t)alen[p0];
+        const uint32_t o0 = i0 - s0;
+        int64_t from = -1;   // input offset of the group's first base, when the group is all bases of one sequence
+        if (o0 + kJoinGroup <= a0) from = src[2 * p0] + o0;
+        else if (o0 > a0 && o0 + kJoinGroup < s1 - s0) from = src[2 * p0 + 1] + (o0 - a0 - 1);
+        if (g0 + kJoinGroup <= cnt && from >= 8 && (uint64_t)from + 16 <= total) {
+            const uintptr_t addr = reinterpret_cast<uintptr_t>(seqs + from);
+            const uint64_t *wd = reinterpret_cast<const uint64_t *>(addr & ~(uintptr_t)7);
+            const uint32_t sh = (uint32_t)(addr & 7u) * 8u;
+            const uint64_t v = sh ? (wd[0] >> sh) | (wd[1] << (64u - sh)) : wd[0];
+            bad |= (v & 0xfcfcfcfcfcfcfcfcull) != 0;
+            const uint32_t tag = 8u * p0 + 1u;
+            uint32_t o[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                o[e] = (tag + (uint32_t)((v >> (16 * e)) & 0xffu)) | ((tag + (uint32_t)((v >> (16 * e + 8)) & 0xffu)) << 16);
+            *reinterpret_cast<uint4 *>(out + i0) = make_uint4(o[0], o[1], o[2], o[3]);   // i0 is a multiple of 8
+            continue;
         }
-        out[i] = (uint16_t)(8u * p + code);
+        for (uint32_t e = 0; e < kJoinGroup && g0 + e < cnt; ++e) {
+            const uint32_t i = i0 + e;
+            const uint32_t q = pair_at(w, s_start, start, P, i, cur), p = w.lo + q;
+            const uint32_t ps = w.lds ? (uint32_t)s_start[q] : (uint32_t)start[p];
+            const uint32_t pe = w.lds ? (uint32_t)s_start[q + 1] : (uint32_t)start[p + 1];
+            const uint32_t a = w.lds ? (uint32_t)s_alen[q] : (uint32_t)alen[p];
+            const uint32_t o = i - ps, plen = pe - ps;
+            uint32_t code;
+            if (o < a) {
+                code = seqs[src[2 * p] + o];
+                bad |= code > 3u;
+                code += 1u;
+            } else if (o == a) {
+                code = 5u;
+            } else if (o + 1 < plen) {
+                code = seqs[src[2 * p + 1] + (o - a - 1)];
+                bad |= code > 3u;
+                code += 1u;
+            } else {
+                code = 6u;
+            }
+            out[i] = (uint16_t)(8u * p + code);
+        }
     }
     if (__any(bad) && dev::lane_id() == 0) atomicOr(err, 1u);
 }
@@ -465,9 +499,13 @@ lor_status batch_overlap_run(const uint8_t *seqs, uint32_t P, uint64_t N, const 
     LOR_HIP(hipMemcpyAsync(alen, h_alen, P * sizeof(int32_t), hipMemcpyHostToDevice, s));
     LOR_HIP(hipMemcpyAsync(src, h_src, 2ull * P * sizeof(int64_t), hipMemcpyHostToDevice, s));
     LOR_TRY(zero_words(hdr, 16, s));
+    // end of the input bytes the pairs use: the last pair's B ends there
+    const uint64_t in_end = P ? (uint64_t)h_src[2 * P - 1] +
+                                    (uint64_t)(h_start[P] - h_start[P - 1] - h_alen[P - 1] - 2)
+                              : 0;
     LOR_LAUNCH("k_join_pairs", 3.0 * N, s,
                hipLaunchKernelGGL(k_join_pairs, dim3(div_up(N, kJoinTile)), dim3(kBlock), 0, s, seqs, start, alen, src, P,
-                                  (uint32_t)N, text, hdr));
+                                  (uint32_t)N, in_end, text, hdr));
     LOR_TRY(dc3_u16(text, (uint32_t)N, 8u * (P - 1) + 6u, sa, ar, hdr, s));
     ar.release(phase);
     LOR_TRY(lcp_build_u16(text, (uint32_t)N, sa, lcp, nullptr, ar, s));
