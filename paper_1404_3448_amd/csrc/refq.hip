@@ -66,21 +66,45 @@ __device__ __forceinline__ uint32_t seq_fast(const int32_t *__restrict__ start, 
     return lo;
 }
 
-// start[j] = joined start of sequence j (0 = reference), start[S] = N.
+// start[j] = joined start of sequence j (0 = reference), start[S] = N. A
+// thread writes kRqJoinBytes consecutive positions; when they are all bases
+// of one sequence they are the input shifted by the sequence index (aligned
+// 8-byte loads, a funnel shift, the base check on whole words), otherwise
+// they go position by position.
+constexpr uint32_t kRqJoinBytes = 16;
+
 __global__ __launch_bounds__(kBlock) void k_rq_join(const uint8_t *__restrict__ seqs, const int32_t *__restrict__ start,
-                                                    const int32_t *__restrict__ tab, uint32_t N,
+                                                    const int32_t *__restrict__ tab, uint32_t N, uint32_t total,
                                                     uint8_t *__restrict__ out, uint32_t *__restrict__ err) {
     uint32_t bad = 0;
-    for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < N; p += gridDim.x * kBlock) {
-        const uint32_t j = seq_fast(start, tab, p);
-        uint32_t c;
-        if (p + 1 == (uint32_t)start[j + 1]) {
-            c = 4u;
-        } else {
-            c = seqs[p - j];
-            bad |= c > 3u;
+    const uint32_t stride = gridDim.x * kBlock * kRqJoinBytes;
+    for (uint32_t p0 = (blockIdx.x * kBlock + threadIdx.x) * kRqJoinBytes; p0 < N; p0 += stride) {
+        uint32_t j = seq_fast(start, tab, p0);
+        const uint32_t from = p0 - j;
+        if (p0 + kRqJoinBytes < (uint32_t)start[j + 1] && from >= 8u && from + 24u <= total) {
+            const uintptr_t addr = reinterpret_cast<uintptr_t>(seqs + from);
+            const uint64_t *w = reinterpret_cast<const uint64_t *>(addr & ~(uintptr_t)7);
+            const uint32_t sh = (uint32_t)(addr & 7u) * 8u;
+            const uint64_t w0 = w[0], w1 = w[1], w2 = w[2];
+            const uint64_t lo = sh ? (w0 >> sh) | (w1 << (64u - sh)) : w0;
+            const uint64_t hi = sh ? (w1 >> sh) | (w2 << (64u - sh)) : w1;
+            bad |= ((lo | hi) & 0xfcfcfcfcfcfcfcfcull) != 0;
+            *reinterpret_cast<uint4 *>(out + p0) =   // p0 is a multiple of 16; the text buffer is 16-byte aligned
+                make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+            continue;
         }
-        out[p] = (uint8_t)c;
+        for (uint32_t u = 0; u < kRqJoinBytes && p0 + u < N; ++u) {
+            const uint32_t p = p0 + u;
+            while ((uint32_t)start[j + 1] <= p) ++j;
+            uint32_t c;
+            if (p + 1 == (uint32_t)start[j + 1]) {
+                c = 4u;
+            } else {
+                c = seqs[p - j];
+                bad |= c > 3u;
+            }
+            out[p] = (uint8_t)c;
+        }
     }
     if (__any(bad) && dev::lane_id() == 0) atomicOr(err, 1u);
 }
@@ -382,8 +406,8 @@ lor_status refq_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t Q,
                hipLaunchKernelGGL(k_rq_buckets, dim3(grid_for(nb + 1)), dim3(kBlock), 0, s, L.start, S, (uint32_t)N,
                                   nb, L.tab));
     LOR_LAUNCH("k_rq_join", 2.0 * N, s,
-               hipLaunchKernelGGL(k_rq_join, dim3(grid_for(N)), dim3(kBlock), 0, s, seqs, L.start, L.tab,
-                                  (uint32_t)N, L.text, hdr));
+               hipLaunchKernelGGL(k_rq_join, dim3(grid_for(div_up(N, kRqJoinBytes))), dim3(kBlock), 0, s, seqs,
+                                  L.start, L.tab, (uint32_t)N, (uint32_t)(N - S), L.text, hdr));
     // symbols byte + 1: bases 1..4, separator 5
     LOR_TRY(dc3_u8(L.text, (uint32_t)N, 5u, L.sa, ar, hdr, s));
     ar.release(phase);
