@@ -529,10 +529,14 @@ template <> struct Rec<uint8_t> { uint4 a; };
 template <> struct Rec<int32_t> { uint4 a, b; };
 template <> struct Rec<uint16_t> { uint4 a, b; };
 
+// For q < n0 it also writes Step 2's pair of the mod-0 suffix 3q: slot[q] =
+// rank of suffix 3q+1 minus one (read from rank12 itself: when n mod 3 = 1
+// the last one is the padding-only position n) and sym0[q] = t_{3q}.
 template <typename CH>
 __global__ __launch_bounds__(kBlock) void k_records(const CH *__restrict__ t, Dims d,
                                                     const int32_t *__restrict__ rank12,
-                                                    Rec<CH> *__restrict__ rec) {
+                                                    Rec<CH> *__restrict__ rec, uint32_t *__restrict__ slot,
+                                                    uint32_t *__restrict__ sym0) {
     const uint32_t nq = d.n0 + 1;
     for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < nq; q += gridDim.x * kBlock) {
         const uint32_t p = 3u * q;
@@ -548,6 +552,10 @@ __global__ __launch_bounds__(kBlock) void k_records(const CH *__restrict__ t, Di
             x.b = make_uint4(r1, r2, r4, 0u);
         }
         rec[q] = x;
+        if (q < d.n0) {
+            slot[q] = (uint32_t)rank12[q] - 1u;
+            sym0[q] = c0;
+        }
     }
 }
 
@@ -613,15 +621,6 @@ __global__ __launch_bounds__(kBlock) void k_ns_count(const int32_t *__restrict__
 // (rank(3q+1) - 1, t_{3q}). A bucketed scatter of these pairs puts t_{3q}
 // at sample-order slot rank(3q+1) - 1, so Step 2 then reads its keys in
 // order instead of gathering one text symbol per mod-0 suffix.
-template <typename CH>
-__global__ __launch_bounds__(kBlock) void k_ns_pairs(const CH *__restrict__ t, Dims d,
-                                                     const int32_t *__restrict__ rank12,
-                                                     uint32_t *__restrict__ slot, uint32_t *__restrict__ sym0) {
-    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < d.n0; q += gridDim.x * kBlock) {
-        slot[q] = (uint32_t)rank12[q] - 1u;
-        sym0[q] = sym(t, d.n, 3u * q);
-    }
-}
 
 // Emit mod-0 position 3*idx (predecessor of mod-1 entry idx) with key
 // t_{3 idx}, which first[r] holds for sample-order slot r. A tile is staged
@@ -1053,18 +1052,19 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     }
     const int32_t *rank12 = R;
 
-    // ---- records for the merge
+    // ---- records for the merge, and Step 2's (slot, first symbol) pairs
     Rec<CH> *rec;
     LOR_TAKE(ar, Rec<CH>, (size_t)d.n0 + 1, rec);
-    if (run)
-        LOR_LAUNCH("k_records", (double)(d.n0 + 1) * (sizeof(Rec<CH>) + 12) + (double)n * sizeof(CH), s,
-                   hipLaunchKernelGGL(k_records<CH>, dim3(grid_for(d.n0 + 1)), dim3(kBlock), 0, s, t, d, rank12,
-                                      rec));
-
-    // ---- Step 2: mod-0 suffixes
     uint32_t *keys0, *vals0, *keys1, *vals1, *sc0, *sc1, *counts2;
     LOR_TAKE(ar, uint32_t, d.n0, keys0);
     LOR_TAKE(ar, uint32_t, d.n0, vals0);
+    if (run)
+        LOR_LAUNCH("k_records", (double)(d.n0 + 1) * (sizeof(Rec<CH>) + 12) + (double)n * sizeof(CH) + 8.0 * d.n0,
+                   s,
+                   hipLaunchKernelGGL(k_records<CH>, dim3(grid_for(d.n0 + 1)), dim3(kBlock), 0, s, t, d, rank12,
+                                      rec, keys0, vals0));
+
+    // ---- Step 2: mod-0 suffixes
     LOR_TAKE(ar, uint32_t, d.n0, keys1);
     LOR_TAKE(ar, uint32_t, d.n0, vals1);
     LOR_TAKE(ar, uint32_t, d.n0, sc0);
@@ -1078,11 +1078,8 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     LOR_TAKE(ar, uint32_t, (size_t)div_up(n, kBlock * 4) + 2, split);
     LOR_TAKE(ar, uint32_t, (size_t)div_up(n, kBlock * 4 * kCoarse) + 2, csplit);
     if (run) {
-        // first symbols of the mod-0 suffixes in sample order, into R (the
-        // ranks are consumed by k_ns_pairs; the records already hold them)
-        LOR_LAUNCH("k_ns_pairs", (double)d.n0 * (12 + sizeof(CH)), s,
-                   hipLaunchKernelGGL(k_ns_pairs<CH>, dim3(grid_for(d.n0)), dim3(kBlock), 0, s, t, d, rank12, keys0,
-                                      vals0));
+        // first symbols of the mod-0 suffixes in sample order, into R (its
+        // ranks were consumed by k_records, which also wrote these pairs)
         uint32_t *const tmp4[4] = {keys1, vals1, sc0, sc1};
         LOR_TRY(bucketed_scatter(R, d.m, keys0, vals0, 0, d.n0, tmp4, counts2, s, false));
         const uint32_t G = scan_groups(d.m);
