@@ -296,22 +296,21 @@ __global__ __launch_bounds__(kMxChunkThreads) void k_mx_chunks(Up *__restrict__ 
 // EMIT 0: fold every credited match of a rank of sequence j != t with target
 // t into best[j * k + t] = max(m << 32 | ~offset). EMIT 1: the rank holding
 // its pair's best key writes the record.
+// (at most 256 VGPRs: 2 waves per SIMD without spills)
 template <int EMIT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_mx_ranks(const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp,
-                                                     uint32_t n, const int32_t *__restrict__ start, uint32_t k,
-                                                     bool vec, uint32_t tiles, uint32_t chunks,
-                                                     const Up *__restrict__ tu,
-                                                     const Dn *__restrict__ td, const Up *__restrict__ cu,
-                                                     const Dn *__restrict__ cd, unsigned long long *__restrict__ best,
-                                                     lor_overlap *__restrict__ out) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_mx_ranks(
+    const int32_t *__restrict__ sa, const int32_t *__restrict__ lcp, uint32_t n, const int32_t *__restrict__ start,
+    uint32_t k, bool vec, uint32_t tiles, uint32_t chunks, const Up *__restrict__ tu, const Dn *__restrict__ td,
+    const Up *__restrict__ cu, const Dn *__restrict__ cd, unsigned long long *__restrict__ best,
+    lor_overlap *__restrict__ out) {
     __shared__ int32_t s_start[kMaxSeqs + 1];
     __shared__ unsigned long long s_best[kMaxSeqs];   // column t of best, this workgroup's copy
     __shared__ Up s_wu[kMxWaves];
     __shared__ Dn s_wd[kMxWaves];
     // EMIT 1: the ranks holding a best key queue {j, neighbour, m, offset};
     // the records are written after the target's walk. A key belongs to one
-    // rank, so a target queues at most k entries. Indexed by target parity:
-    // a queue is cleared two targets after it was read.
+    // rank, so a target queues at most k entries. Indexed by target parity,
+    // so a queue is cleared only when no thread can still be reading it.
     __shared__ int4 s_q[2][kMaxSeqs];
     __shared__ uint32_t s_nq[2];
     if (threadIdx.x < 2) s_nq[threadIdx.x] = 0;
@@ -324,7 +323,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
     for (uint32_t t = 0; t < k; ++t) {
         const int32_t ti = (int32_t)t;
         const uint32_t buf = t & 1u;
-        if (EMIT == 1 && threadIdx.x == 0 && t >= 1) s_nq[buf ^ 1u] = 0;   // read before the last barrier
+        // this target's queue was last read for target t - 2, by every thread
+        // before the barrier that ended target t - 1; it is filled only after
+        // the next barrier
+        if (EMIT == 1 && threadIdx.x == 0 && t >= 2) s_nq[buf] = 0;
         // carries of everything before and after the tile (two-level scan)
         const Up carry_u = up_comb(cu[(size_t)t * chunks + c], tu[(size_t)t * tiles + tile]);
         const Dn carry_d = dn_comb(td[(size_t)t * tiles + tile], cd[(size_t)t * chunks + c]);
@@ -405,7 +407,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
             const int32_t down_at = after ? (int32_t)(r0 + __ffs(after) - 1u) : in_first;
             const int32_t at = (from_up >> i) & 1u ? up_at : down_at;   // the neighbour that gave m
             const uint32_t q = atomicAdd(&s_nq[buf], 1u);
-            if (q < kMaxSeqs) s_q[buf][q] = make_int4(j, at, (int32_t)(key >> 32), (int32_t)(0xffffffffu - (uint32_t)key));
+            if (q < kMaxSeqs)
+                s_q[buf][q] = make_int4(j, at, (int32_t)(key >> 32), (int32_t)(0xffffffffu - (uint32_t)key));
         }
         __syncthreads();
         if (EMIT == 1) {
