@@ -125,8 +125,11 @@ __global__ __launch_bounds__(kBlock) void k_join_pairs(const uint8_t *__restrict
             const uint32_t tag = 8u * p0 + 1u;
             uint32_t o[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                o[e] = (tag + (uint32_t)((v >> (16 * e)) & 0xffu)) | ((tag + (uint32_t)((v >> (16 * e + 8)) & 0xffu)) << 16);
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t lo = tag + (uint32_t)((v >> (16 * e)) & 0xffu);
+                const uint32_t hi = tag + (uint32_t)((v >> (16 * e + 8)) & 0xffu);
+                o[e] = lo | (hi << 16);
+            }
             *reinterpret_cast<uint4 *>(out + i0) = make_uint4(o[0], o[1], o[2], o[3]);   // i0 is a multiple of 8
             continue;
         }
@@ -504,8 +507,8 @@ lor_status batch_overlap_run(const uint8_t *seqs, uint32_t P, uint64_t N, const 
                                     (uint64_t)(h_start[P] - h_start[P - 1] - h_alen[P - 1] - 2)
                               : 0;
     LOR_LAUNCH("k_join_pairs", 3.0 * N, s,
-               hipLaunchKernelGGL(k_join_pairs, dim3(div_up(N, kJoinTile)), dim3(kBlock), 0, s, seqs, start, alen, src, P,
-                                  (uint32_t)N, in_end, text, hdr));
+               hipLaunchKernelGGL(k_join_pairs, dim3(div_up(N, kJoinTile)), dim3(kBlock), 0, s, seqs, start, alen, src,
+                                  P, (uint32_t)N, in_end, text, hdr));
     LOR_TRY(dc3_u16(text, (uint32_t)N, 8u * (P - 1) + 6u, sa, ar, hdr, s));
     ar.release(phase);
     LOR_TRY(lcp_build_u16(text, (uint32_t)N, sa, lcp, nullptr, ar, s));

@@ -348,8 +348,8 @@ lor_status rq_carve(Arena &ar, uint64_t N, uint32_t S, RqLayout *L) {
 // Matches of every other sequence's suffixes with one target sequence:
 // tile states, their scan, then the two per-rank passes.
 lor_status target_scan(const int32_t *sa, const int32_t *lcp, uint32_t n, Target tg, const int32_t *start,
-                       const int32_t *tab, uint32_t S, uint32_t stride, int32_t base, Fwd *tf, Bwd *tb, unsigned long long *best,
-                       lor_overlap *out, hipStream_t s) {
+                       const int32_t *tab, uint32_t S, uint32_t stride, int32_t base, Fwd *tf, Bwd *tb,
+                       unsigned long long *best, lor_overlap *out, hipStream_t s) {
     const uint32_t tiles = div_up(n, kRqTile);
     LOR_LAUNCH("k_rq_tiles", 8.0 * n, s,
                hipLaunchKernelGGL(k_rq_tiles, dim3(tiles), dim3(kBlock), 0, s, sa, lcp, n, tg, tf, tb));
@@ -357,8 +357,8 @@ lor_status target_scan(const int32_t *sa, const int32_t *lcp, uint32_t n, Target
                hipLaunchKernelGGL(k_rq_tile_scan, dim3(1), dim3(kRqScanThreads), 0, s, tf, tb, tiles));
     for (int emit = 0; emit < 2; ++emit)
         LOR_LAUNCH("k_rq_ranks", 8.0 * n, s,
-                   hipLaunchKernelGGL(k_rq_ranks, dim3(tiles), dim3(kBlock), 0, s, sa, lcp, n, tg, start, tab, S, tf, tb,
-                                      emit, stride, base, best, out));
+                   hipLaunchKernelGGL(k_rq_ranks, dim3(tiles), dim3(kBlock), 0, s, sa, lcp, n, tg, start, tab, S, tf,
+                                      tb, emit, stride, base, best, out));
     return LOR_OK;
 }
 
