@@ -65,6 +65,16 @@ def test_ref_random_small(seed):
     check(ref, queries, run(ref, queries))
 
 
+def test_ref_many_tiny_queries():
+    """20,000 queries of 0-3 bases: a 64-position bucket of the sequence
+    lookup then holds dozens of query starts, so every lookup searches
+    inside its bucket, and empty queries are pure separators."""
+    rng = np.random.default_rng(911)
+    ref = rng.integers(0, 4, size=300, dtype=np.uint8)
+    queries = [rng.integers(0, 4, size=int(rng.integers(0, 4)), dtype=np.uint8) for _ in range(20000)]
+    check(ref, queries, run(ref, queries))
+
+
 def test_ref_noncoding_many_queries():
     rng = synth.rng_for(77)
     ref = synth.noncoding_like(rng, 100_000)
