@@ -90,6 +90,19 @@ def test_matrix_max_sequences():
     check(seqs)
 
 
+@pytest.mark.parametrize("lengths", [(4000, 4190), (4000, 4000, 4285), (4095,)])
+def test_matrix_exact_tiles(lengths):
+    """Joined lengths that are whole 4096-rank tiles (8192, 12288, 4096): no
+    ragged last tile, and with one sequence no target has another to meet."""
+    rng = np.random.default_rng(sum(lengths))
+    seqs = [rng.integers(0, 4, size=m, dtype=np.uint8) for m in lengths]
+    for i in range(1, len(seqs)):
+        s = int(rng.integers(0, seqs[0].size - 300))
+        seqs[i][100:300] = seqs[0][s:s + 200]
+    assert (sum(lengths) + len(lengths)) % 4096 == 0
+    check(seqs)
+
+
 def test_matrix_noncoding():
     rng = synth.rng_for(91)
     seqs = [synth.noncoding_like(rng, int(rng.integers(1000, 20000))) for _ in range(8)]
