@@ -552,7 +552,7 @@ __global__ __launch_bounds__(kBlock) void k_records(const CH *__restrict__ t, Di
             x.b = make_uint4(r1, r2, r4, 0u);
         }
         rec[q] = x;
-        if (q < d.n0) {
+        if (slot && q < d.n0) {
             slot[q] = (uint32_t)rank12[q] - 1u;
             sym0[q] = c0;
         }
@@ -684,6 +684,310 @@ __global__ __launch_bounds__(kBlock) void k_ns_write(const int32_t *__restrict__
     }
 }
 
+// ------------------- Step 1 at deep levels: order from the parent level
+//
+// A level's text is the name array R of its parent, and the parent sorted
+// its triples before naming them: its sample order (kept in this level's SA
+// buffer until the merge writes it) lists this level's text positions by
+// symbol value, and its names in that order are this level's symbols in that
+// order. Keeping the positions i mod 3 != 0 gives the sample positions
+// sorted by their first symbol s0 with no sort at all (the padding-only
+// position, triple (0, 0, 0), goes first). When the parent's names are
+// nearly all distinct (the texts of deep levels), only the runs of equal s0
+// still need an order, by (s1, s2): that subset is sorted on its own and put
+// back into its runs' slots.
+
+// Sample positions in P (text positions sorted by symbol), per group of tiles.
+__global__ __launch_bounds__(kBlock) void k_po_count(const int32_t *__restrict__ P, uint32_t n, uint32_t groups,
+                                                     uint32_t *__restrict__ counts) {
+    __shared__ uint32_t s_tmp[kBlock / kWave];
+    uint32_t t0, t1;
+    group_tiles(n, groups, blockIdx.x, &t0, &t1);
+    uint32_t c = 0;
+    for (uint32_t r = t0 * kScanTile + threadIdx.x; r < min(n, t1 * kScanTile); r += kBlock)
+        c += ((uint32_t)P[r] % 3u) != 0u;
+    uint32_t tot;
+    dev::block_exclusive_sum(c, s_tmp, &tot);
+    if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+}
+
+// ord[k] = R-index of the k-th sample position in s0 order, s0v[k] = its s0
+// (from the parent's names in the same order). Tiles are staged in LDS.
+__global__ __launch_bounds__(kBlock) void k_po_write(const int32_t *__restrict__ P, const uint32_t *__restrict__ NS,
+                                                     Dims d, uint32_t groups, const uint32_t *__restrict__ counts,
+                                                     int32_t *__restrict__ ord, uint32_t *__restrict__ s0v) {
+    __shared__ uint32_t s_tmp[kBlock / kWave];
+    __shared__ __align__(16) uint32_t s_p[kScanTile];
+    __shared__ __align__(16) uint32_t s_ns[kScanTile];
+    __shared__ uint32_t s_k[kScanTile];
+    __shared__ uint32_t s_v[kScanTile];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && d.dummy) {
+        ord[0] = (int32_t)(d.n0 - 1);   // position n: triple (0, 0, 0), below every other
+        s0v[0] = 0;
+    }
+    uint32_t t0, t1;
+    group_tiles(d.n, groups, blockIdx.x, &t0, &t1);
+    uint32_t base = d.dummy + counts[blockIdx.x];
+    for (uint32_t tile = t0; tile < t1; ++tile) {
+        const uint32_t g0 = tile * kScanTile;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint32_t l = i * kBlock + threadIdx.x, r = g0 + l;
+            const bool ok = r < d.n;
+            s_p[l] = ok ? (uint32_t)P[r] : 0u;   // position 0 is not a sample position: padding drops out
+            s_ns[l] = ok ? NS[r] : 0u;
+        }
+        __syncthreads();
+        const uint32_t l0 = threadIdx.x * kScanItems;
+        uint32_t p[kScanItems], ns[kScanItems];
+#pragma unroll
+        for (int h = 0; h < kScanItems / 4; ++h) {
+            const uint4 a = *reinterpret_cast<const uint4 *>(&s_p[l0 + 4 * h]);
+            const uint4 f = *reinterpret_cast<const uint4 *>(&s_ns[l0 + 4 * h]);
+            p[4 * h] = a.x; p[4 * h + 1] = a.y; p[4 * h + 2] = a.z; p[4 * h + 3] = a.w;
+            ns[4 * h] = f.x; ns[4 * h + 1] = f.y; ns[4 * h + 2] = f.z; ns[4 * h + 3] = f.w;
+        }
+        uint32_t c = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) c += (p[i] % 3u) != 0u;
+        uint32_t tot;
+        uint32_t jl = dev::block_exclusive_sum(c, s_tmp, &tot);
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint32_t cls = p[i] % 3u;
+            if (cls != 0u) {
+                s_k[jl] = cls == 1u ? p[i] / 3u : d.n0 + p[i] / 3u;
+                s_v[jl] = ns[i];
+                ++jl;
+            }
+        }
+        __syncthreads();
+        for (uint32_t x = threadIdx.x; x < tot; x += kBlock) {
+            const uint32_t j = base + x;
+            if (j < d.m) {
+                ord[j] = (int32_t)s_k[x];
+                s0v[j] = s_v[x];
+            }
+        }
+        base += tot;
+        __syncthreads();   // the next tile reuses the LDS
+    }
+}
+
+// Entry k of the s0 order shares its s0 with a neighbour.
+__device__ __forceinline__ bool po_in_run(const uint32_t *s0v, uint32_t m, uint32_t k) {
+    const uint32_t x = s0v[k];
+    return (k > 0 && s0v[k - 1] == x) || (k + 1 < m && s0v[k + 1] == x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_po_runs_count(const uint32_t *__restrict__ s0v, uint32_t m,
+                                                          uint32_t groups, uint32_t *__restrict__ counts) {
+    __shared__ uint32_t s_tmp[kBlock / kWave];
+    uint32_t t0, t1;
+    group_tiles(m, groups, blockIdx.x, &t0, &t1);
+    uint32_t c = 0;
+    for (uint32_t k = t0 * kScanTile + threadIdx.x; k < min(m, t1 * kScanTile); k += kBlock) c += po_in_run(s0v, m, k);
+    uint32_t tot;
+    dev::block_exclusive_sum(c, s_tmp, &tot);
+    if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+}
+
+// The subset (entries in runs of equal s0), in order: its slot k and ord[k];
+// flag[k] (nullable) = 1 (a new name) for every entry outside the subset, 0
+// inside (set later from the subset's order).
+__global__ __launch_bounds__(kBlock) void k_po_runs_write(const uint32_t *__restrict__ s0v,
+                                                          const int32_t *__restrict__ ord, uint32_t m,
+                                                          uint32_t groups, const uint32_t *__restrict__ counts,
+                                                          uint32_t cap, uint32_t *__restrict__ sub_slot,
+                                                          uint32_t *__restrict__ sub_idx,
+                                                          uint32_t *__restrict__ flag) {
+    __shared__ uint32_t s_tmp[kBlock / kWave];
+    uint32_t t0, t1;
+    group_tiles(m, groups, blockIdx.x, &t0, &t1);
+    uint32_t base = counts[blockIdx.x];
+    for (uint32_t tile = t0; tile < t1; ++tile) {
+        const uint32_t k0 = tile * kScanTile + threadIdx.x * kScanItems;
+        bool in[kScanItems];
+        uint32_t c = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint32_t k = k0 + i;
+            in[i] = k < m && po_in_run(s0v, m, k);
+            c += in[i];
+            if (flag && k < m) flag[k] = in[i] ? 0u : 1u;
+        }
+        uint32_t tot;
+        uint32_t j = base + dev::block_exclusive_sum(c, s_tmp, &tot);
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            if (in[i]) {
+                if (j < cap) {   // the host checks the count against cap before using the subset
+                    sub_slot[j] = k0 + i;
+                    sub_idx[j] = (uint32_t)ord[k0 + i];
+                }
+                ++j;
+            }
+        }
+        base += tot;
+    }
+}
+
+// First stage of the subset's sort: keys (t_{i+1}, t_{i+2}) of its positions.
+template <typename CH>
+__global__ __launch_bounds__(kBlock) void k_po_keys(const CH *__restrict__ t, Dims d, int b,
+                                                    const uint32_t *__restrict__ sub_idx, uint32_t ms,
+                                                    uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < ms; j += gridDim.x * kBlock) {
+        const uint32_t idx = min(sub_idx[j], d.m - 1);
+        const uint32_t p = d.pos_of(idx);
+        keys[j] = ((uint64_t)sym(t, d.n, p + 1) << b) | (uint64_t)sym(t, d.n, p + 2);
+        vals[j] = idx;
+    }
+}
+
+// The subset, sorted by whole triples (keys: s0 << 32 | rank of (s1, s2)),
+// goes back into its slots in order; an entry starts a new name when its
+// triple differs from the subset entry before it.
+__global__ __launch_bounds__(kBlock) void k_po_place(const uint64_t *__restrict__ keys,
+                                                     const uint32_t *__restrict__ vals,
+                                                     const uint32_t *__restrict__ sub_slot, uint32_t ms, uint32_t m,
+                                                     int32_t *__restrict__ sa12, uint32_t *__restrict__ flag) {
+    for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < ms; j += gridDim.x * kBlock) {
+        const uint32_t k = sub_slot[j];
+        if (k < m) {
+            sa12[k] = (int32_t)vals[j];
+            flag[k] = (j == 0 || keys[j] != keys[j - 1]) ? 1u : 0u;
+        }
+    }
+}
+
+// names[k] = 1-based name of sorted entry k from the new-name flags (tiles
+// staged in LDS, as k_name_write).
+__global__ __launch_bounds__(kBlock) void k_flag_count(const uint32_t *__restrict__ flag, uint32_t m, uint32_t groups,
+                                                       uint32_t *__restrict__ counts) {
+    __shared__ uint32_t s_tmp[kBlock / kWave];
+    uint32_t t0, t1;
+    group_tiles(m, groups, blockIdx.x, &t0, &t1);
+    uint32_t c = 0;
+    for (uint32_t k = t0 * kScanTile + threadIdx.x; k < min(m, t1 * kScanTile); k += kBlock) c += flag[k];
+    uint32_t tot;
+    dev::block_exclusive_sum(c, s_tmp, &tot);
+    if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_flag_write(const uint32_t *__restrict__ flag, uint32_t m, uint32_t groups,
+                                                       const uint32_t *__restrict__ counts,
+                                                       uint32_t *__restrict__ names) {
+    __shared__ uint32_t s_tmp[kBlock / kWave];
+    __shared__ __align__(16) uint32_t s_f[kScanTile];
+    uint32_t t0, t1;
+    group_tiles(m, groups, blockIdx.x, &t0, &t1);
+    uint32_t base = counts[blockIdx.x];
+    for (uint32_t tile = t0; tile < t1; ++tile) {
+        const uint32_t g0 = tile * kScanTile;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint32_t l = i * kBlock + threadIdx.x;
+            s_f[l] = g0 + l < m ? flag[g0 + l] : 0u;
+        }
+        __syncthreads();
+        const uint32_t l0 = threadIdx.x * kScanItems;
+        uint32_t f[kScanItems], c = 0;
+#pragma unroll
+        for (int h = 0; h < kScanItems / 4; ++h) {
+            const uint4 a = *reinterpret_cast<const uint4 *>(&s_f[l0 + 4 * h]);
+            f[4 * h] = a.x; f[4 * h + 1] = a.y; f[4 * h + 2] = a.z; f[4 * h + 3] = a.w;
+        }
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) c += f[i];
+        uint32_t tot;
+        uint32_t name = base + dev::block_exclusive_sum(c, s_tmp, &tot);
+        __syncthreads();   // every thread has read its flags: the tile is rewritten with names
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            name += f[i];
+            s_f[l0 + i] = name;
+        }
+        __syncthreads();
+        for (uint32_t l = threadIdx.x; l < kScanTile; l += kBlock)
+            if (g0 + l < m) names[g0 + l] = s_f[l];
+        base += tot;
+        __syncthreads();   // the next tile reuses the LDS
+    }
+}
+
+// Step 2 from the parent's order: the mod-0 positions of P, in order, with
+// their symbols (ties of the symbol then need the rank of the next suffix).
+__global__ __launch_bounds__(kBlock) void k_po0_count(const int32_t *__restrict__ P, uint32_t n, uint32_t groups,
+                                                      uint32_t *__restrict__ counts) {
+    __shared__ uint32_t s_tmp[kBlock / kWave];
+    uint32_t t0, t1;
+    group_tiles(n, groups, blockIdx.x, &t0, &t1);
+    uint32_t c = 0;
+    for (uint32_t r = t0 * kScanTile + threadIdx.x; r < min(n, t1 * kScanTile); r += kBlock)
+        c += ((uint32_t)P[r] % 3u) == 0u;
+    uint32_t tot;
+    dev::block_exclusive_sum(c, s_tmp, &tot);
+    if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_po0_write(const int32_t *__restrict__ P, const uint32_t *__restrict__ NS,
+                                                      Dims d, uint32_t groups, const uint32_t *__restrict__ counts,
+                                                      uint32_t *__restrict__ pos0, uint32_t *__restrict__ sym0) {
+    __shared__ uint32_t s_tmp[kBlock / kWave];
+    uint32_t t0, t1;
+    group_tiles(d.n, groups, blockIdx.x, &t0, &t1);
+    uint32_t base = counts[blockIdx.x];
+    for (uint32_t tile = t0; tile < t1; ++tile) {
+        const uint32_t r0 = tile * kScanTile + threadIdx.x * kScanItems;
+        uint32_t p[kScanItems];
+        bool keep[kScanItems];
+        uint32_t c = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            p[i] = r0 + i < d.n ? (uint32_t)P[r0 + i] : 1u;
+            keep[i] = (p[i] % 3u) == 0u;
+            c += keep[i];
+        }
+        uint32_t tot;
+        uint32_t j = base + dev::block_exclusive_sum(c, s_tmp, &tot);
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            if (keep[i]) {
+                if (j < d.n0) {
+                    pos0[j] = p[i];
+                    sym0[j] = NS[r0 + i];
+                }
+                ++j;
+            }
+        }
+        base += tot;
+    }
+}
+
+// Keys of the Step 2 subset: (t_j, rank of suffix j + 1) for mod-0 position j.
+__global__ __launch_bounds__(kBlock) void k_po0_keys(const uint32_t *__restrict__ sym0,
+                                                     const uint32_t *__restrict__ sub_slot,
+                                                     const uint32_t *__restrict__ sub_pos, uint32_t ms,
+                                                     const int32_t *__restrict__ rank12, Dims d,
+                                                     uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < ms; j += gridDim.x * kBlock) {
+        const uint32_t p = sub_pos[j];
+        const uint32_t q = min(p / 3u, d.n0 - 1u);   // R-index of position p + 1 (the padding position when p + 1 = n)
+        keys[j] = ((uint64_t)sym0[min(sub_slot[j], d.n0 - 1u)] << 32) | (uint32_t)rank12[q];
+        vals[j] = p;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_po0_place(const uint32_t *__restrict__ vals,
+                                                      const uint32_t *__restrict__ sub_slot, uint32_t ms, uint32_t n0,
+                                                      uint32_t *__restrict__ pos0) {
+    for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < ms; j += gridDim.x * kBlock) {
+        const uint32_t k = sub_slot[j];
+        if (k < n0) pos0[k] = vals[j];
+    }
+}
+
 // ------------------------------------------------------ Step 3: merge
 
 // A = mod-0 positions sorted (Step 2), B = sample order without the padding
@@ -785,19 +1089,41 @@ struct HostHdr {
     uint32_t maxname;
 };
 
-// Replayed launch sequences: flag the header when this level's name count
-// differs from the recorded one (lane 0 stores; vector memory only).
-__global__ __launch_bounds__(kWave) void k_expect_names(uint32_t *hdr, uint32_t expected) {
-    if (threadIdx.x == 0 && hdr[1] != expected) hdr[kStaleWord] = 1u;
+// Replayed launch sequences: flag the header when a count the host decided
+// on (header word `word`) differs from the recorded one (lane 0 stores;
+// vector memory only).
+__global__ __launch_bounds__(kWave) void k_expect_names(uint32_t *hdr, int word, uint32_t expected) {
+    if (threadIdx.x == 0 && hdr[word] != expected) hdr[kStaleWord] = 1u;
 }
 
 thread_local DecisionTape *t_tape = nullptr;
+
+// A count the host needs to size launches (header word `word`): read back,
+// or under a replayed launch sequence taken from the tape and checked on the
+// device.
+lor_status decided_count(uint32_t *hdr, int word, uint32_t *out, hipStream_t s) {
+    DecisionTape *tape = t_tape;
+    if (tape && tape->replay) {
+        if (tape->next >= tape->names.size()) {
+            set_error("internal: launch sequence longer than the recorded one");
+            return LOR_EINVAL;
+        }
+        *out = tape->names[tape->next++];
+        LOR_LAUNCH("k_expect_names", 8.0, s,
+                   hipLaunchKernelGGL(k_expect_names, dim3(1), dim3(kWave), 0, s, hdr, word, *out));
+        return LOR_OK;
+    }
+    LOR_HIP(hipMemcpyAsync(out, hdr + word, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    LOR_HIP(hipStreamSynchronize(s));
+    if (tape) tape->names.push_back(*out);
+    return LOR_OK;
+}
 
 enum KeyMode { KM_U32, KM_U64, KM_STAGED };
 
 template <typename CH>
 lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Arena &ar, uint32_t *hdr,
-                     hipStream_t s, int depth) {
+                     hipStream_t s, int depth, const uint32_t *pnames) {
     if (n == 0) return LOR_OK;
     if (depth > 64) {
         set_error("DC3 recursion deeper than 64 levels");
@@ -812,7 +1138,6 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     int32_t *sa12;     // sample order as R-indices
     LOR_TAKE(ar, int32_t, d.m, R);
     LOR_TAKE(ar, int32_t, d.m, sa12);
-    const size_t mark_tmp = ar.mark();
 
     // ---- Step 1: sort the sample triples
     const int kb = Triple<CH>::key_bits(b);
@@ -832,6 +1157,27 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     }
     KeyMode km = (kbs <= 32) ? KM_U32 : (kbs <= 64 ? KM_U64 : KM_STAGED);
     if (!run) km = KM_U64;   // measuring: the largest footprint
+
+    // Byte and int32 texts name through mixed-radix codes (A^3 of them) with
+    // word-window reads when the text is aligned for them; the pair-tagged
+    // texts of the batched path keep their b-bit packed keys.
+    const uint64_t A = (uint64_t)alphabet + 1;
+    const bool windowed = sizeof(CH) != 2 && A <= 1625 &&   // A^3 < 2^32
+                          ((uintptr_t)t % (sizeof(CH) == 1 ? 4 : 16)) == 0;
+    const uint64_t code_space = windowed ? A * A * A : (kb <= 24 ? (1ull << kb) : ~0ull);
+    const bool use_table = run && code_space <= (1ull << 24) && code_space <= 2ull * d.m + 65536ull;
+    // Order from the parent (see k_po_write): this level's text is the
+    // parent's names, so when at least 7/8 of the n symbols are distinct,
+    // at most 2 (n - alphabet) <= n / 4 positions share their first symbol
+    // with another and go through the sort.
+    const bool parent_order = run && sizeof(CH) == 4 && pnames != nullptr && !use_table && d.m >= 2 &&
+                              (uint64_t)alphabet * 8 >= (uint64_t)n * 7;
+    // Names of the sorted triples in sorted order, kept through the recursion
+    // for the child level's order (levels that sort keep them).
+    uint32_t *keep = nullptr;
+    if (!use_table) LOR_TAKE(ar, uint32_t, d.m, keep);
+    const size_t mark_tmp = ar.mark();
+
     uint32_t *counts;
     LOR_TAKE(ar, uint32_t, radix_counts_words(d.m) + kMaxScanGroups + 64, counts);
     uint32_t *gcount = counts + radix_counts_words(d.m);
@@ -844,15 +1190,99 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     const uint32_t g_el = grid_for(d.m);
     uint32_t hmax = 0;
 
-    // Byte and int32 texts name through mixed-radix codes (A^3 of them) with
-    // word-window reads when the text is aligned for them; the pair-tagged
-    // texts of the batched path keep their b-bit packed keys.
-    const uint64_t A = (uint64_t)alphabet + 1;
-    const bool windowed = sizeof(CH) != 2 && A <= 1625 &&   // A^3 < 2^32
-                          ((uintptr_t)t % (sizeof(CH) == 1 ? 4 : 16)) == 0;
-    const uint64_t code_space = windowed ? A * A * A : (kb <= 24 ? (1ull << kb) : ~0ull);
-    const bool use_table = run && code_space <= (1ull << 24) && code_space <= 2ull * d.m + 65536ull;
-    if (use_table) {
+    // Subset of the parent-order path: at most n / 4 entries (see above).
+    const uint32_t ms_cap = min(d.m, d.n / 4u + 2u);
+    if (parent_order || !run) {
+        const size_t mk = ar.mark();
+        uint32_t *s0v, *flag, *x4, *sub_slot, *sub_idx;
+        LOR_TAKE(ar, uint32_t, d.m, s0v);
+        LOR_TAKE(ar, uint32_t, d.m, flag);
+        LOR_TAKE(ar, uint32_t, d.m, x4);
+        LOR_TAKE(ar, uint32_t, ms_cap, sub_slot);
+        LOR_TAKE(ar, uint32_t, ms_cap, sub_idx);
+        const uint32_t Gn = scan_groups(d.n), Gm = scan_groups(d.m);
+        if (run) {
+            LOR_LAUNCH("k_po_count", 4.0 * d.n, s,
+                       hipLaunchKernelGGL(k_po_count, dim3(Gn), dim3(kBlock), 0, s, sa, d.n, Gn, gcount));
+            LOR_TRY(scan_block_totals(gcount, Gn, nullptr, s));
+            LOR_LAUNCH("k_po_write", 8.0 * d.n + 8.0 * d.m, s,
+                       hipLaunchKernelGGL(k_po_write, dim3(Gn), dim3(kBlock), 0, s, sa, pnames, d, Gn, gcount, sa12,
+                                          s0v));
+            LOR_LAUNCH("k_po_runs_count", 4.0 * d.m, s,
+                       hipLaunchKernelGGL(k_po_runs_count, dim3(Gm), dim3(kBlock), 0, s, s0v, d.m, Gm, gcount));
+            LOR_TRY(scan_block_totals(gcount, Gm, hdr + 3, s));
+            LOR_LAUNCH("k_po_runs_write", 8.0 * d.m, s,
+                       hipLaunchKernelGGL(k_po_runs_write, dim3(Gm), dim3(kBlock), 0, s, s0v, sa12, d.m, Gm, gcount,
+                                          ms_cap, sub_slot, sub_idx, flag));
+        }
+        uint32_t ms = ms_cap;
+        if (run) {
+            LOR_TRY(decided_count(hdr, 3, &ms, s));
+            if (ms > ms_cap) {
+                set_error("internal: %u of %u sample triples share a first symbol (at most %u expected)", ms, d.m,
+                          ms_cap);
+                return LOR_EINVAL;
+            }
+        }
+        if (ms > 0) {
+            uint64_t *sk0, *sk1;
+            uint32_t *sv0, *sv1, *saux, *scnt;
+            LOR_TAKE(ar, uint64_t, ms, sk0);
+            LOR_TAKE(ar, uint64_t, ms, sk1);
+            LOR_TAKE(ar, uint32_t, ms, sv0);
+            LOR_TAKE(ar, uint32_t, ms, sv1);
+            LOR_TAKE(ar, uint32_t, ms, saux);
+            LOR_TAKE(ar, uint32_t, radix_counts_words(ms) + kMaxScanGroups + 64, scnt);
+            if (run) {
+                uint32_t *sg = scnt + radix_counts_words(ms);
+                uint64_t *kc = sk0, *ka = sk1;
+                uint32_t *vc = sv0, *va = sv1;
+                bool alt = false;
+                auto swap_if = [&](bool x) {
+                    if (x) {
+                        uint64_t *y = kc; kc = ka; ka = y;
+                        uint32_t *z = vc; vc = va; va = z;
+                    }
+                };
+                LOR_LAUNCH("k_po_keys", 12.0 * ms, s,
+                           hipLaunchKernelGGL(k_po_keys<CH>, dim3(grid_for(ms)), dim3(kBlock), 0, s, t, d, b, sub_idx,
+                                              ms, kc, vc));
+                LOR_TRY(radix_sort<uint64_t>(kc, vc, ka, va, ms, 0, 2 * b, scnt, s, &alt));
+                swap_if(alt);
+                const uint32_t Gs = scan_groups(ms);
+                LOR_LAUNCH("k_name_count", (double)ms * 8, s,
+                           hipLaunchKernelGGL(k_name_count<uint64_t>, dim3(Gs), dim3(kBlock), 0, s, kc, ms, Gs, sg));
+                LOR_TRY(scan_block_totals(sg, Gs, nullptr, s));
+                LOR_LAUNCH("k_name_write", (double)ms * 12, s,
+                           hipLaunchKernelGGL(k_name_write<uint64_t>, dim3(Gs), dim3(kBlock), 0, s, kc, ms, Gs, sg,
+                                              saux));
+                Dims ds = d;
+                ds.m = ms;   // k_pair_rekey walks the subset
+                LOR_LAUNCH("k_pair_rekey", (double)ms * 16 + (double)ms * sizeof(CH), s,
+                           hipLaunchKernelGGL(k_pair_rekey<CH>, dim3(grid_for(ms)), dim3(kBlock), 0, s, t, ds, vc, saux,
+                                              kc));
+                LOR_TRY(radix_sort<uint64_t>(kc, vc, ka, va, ms, 32, 32 + b, scnt, s, &alt));
+                swap_if(alt);
+                LOR_LAUNCH("k_po_place", 20.0 * ms, s,
+                           hipLaunchKernelGGL(k_po_place, dim3(grid_for(ms)), dim3(kBlock), 0, s, kc, vc, sub_slot, ms,
+                                              d.m, sa12, flag));
+            }
+        }
+        if (run) {
+            LOR_LAUNCH("k_flag_count", 4.0 * d.m, s,
+                       hipLaunchKernelGGL(k_flag_count, dim3(Gm), dim3(kBlock), 0, s, flag, d.m, Gm, gcount));
+            LOR_TRY(scan_block_totals(gcount, Gm, hdr + 1, s));
+            LOR_LAUNCH("k_flag_write", 8.0 * d.m, s,
+                       hipLaunchKernelGGL(k_flag_write, dim3(Gm), dim3(kBlock), 0, s, flag, d.m, Gm, gcount, keep));
+            uint32_t *const tmp4[4] = {s0v, flag, tmpv, x4};
+            LOR_TRY(bucketed_scatter(R, d.m, (const uint32_t *)sa12, keep, 0, d.m, tmp4, counts, s, true));
+        } else {
+            ar.release(mk);   // measuring: the sort branch below is measured too
+        }
+    }
+    if (parent_order) {
+        // named above
+    } else if (use_table) {
         const uint32_t words = max(1u, (uint32_t)div_up(code_space, 32));
         uint32_t *bitmap, *below, *stmp;
         LOR_TAKE(ar, uint32_t, words, bitmap);
@@ -952,10 +1382,9 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
                 set_error("internal: sorted sample order not in its buffer");
                 return LOR_EINVAL;
             }
-            // free now: the other key buffer (2 x m words) and the other value buffer
-            uint32_t *names = reinterpret_cast<uint32_t *>(ka);
-            // scatter buffers: the rest of ka, va, and kc once the names are out
-            uint32_t *const tmp4[4] = {names + d.m, va, reinterpret_cast<uint32_t *>(kc),
+            // names go to `keep`; scatter buffers: ka (2 x m words), va, and kc once the names are out
+            uint32_t *names = keep;
+            uint32_t *const tmp4[4] = {reinterpret_cast<uint32_t *>(ka), va, reinterpret_cast<uint32_t *>(kc),
                                        reinterpret_cast<uint32_t *>(kc) + d.m};
             LOR_LAUNCH("k_name_count", (double)d.m * 8, s,
                        hipLaunchKernelGGL(k_name_count<uint64_t>, dim3(G), dim3(kBlock), 0, s, kc, d.m, G, gcount));
@@ -986,7 +1415,7 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
                 set_error("internal: sorted sample order not in its buffer");
                 return LOR_EINVAL;
             }
-            uint32_t *names = ka;
+            uint32_t *names = keep;
             uint32_t *const tmp4[4] = {va, aux, aux2, kc};   // kc is free once the names are out
             const uint32_t G = scan_groups(d.m);
             LOR_LAUNCH("k_name_count", (double)d.m * 4, s,
@@ -1011,7 +1440,7 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
             h.error = 0;
             h.maxname = tape->names[tape->next++];
             LOR_LAUNCH("k_expect_names", 8.0, s,
-                       hipLaunchKernelGGL(k_expect_names, dim3(1), dim3(kWave), 0, s, hdr, h.maxname));
+                       hipLaunchKernelGGL(k_expect_names, dim3(1), dim3(kWave), 0, s, hdr, 1, h.maxname));
         } else {
             LOR_HIP(hipMemcpyAsync(&h, hdr, sizeof(h), hipMemcpyDeviceToHost, s));
             LOR_HIP(hipStreamSynchronize(s));
@@ -1029,8 +1458,10 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
         unique = (hmax == d.m);
         if (trace_on())
             fprintf(stderr, "[lor] dc3 level %d: n=%u m=%u bits/sym=%d %s passes=%d names=%u%s\n", depth, n, d.m, b,
-                    use_table ? "bitmap-naming" : (km == KM_U32 ? "sort-u32" : km == KM_U64 ? "sort-u64" : "sort-2stage"),
-                    use_table ? 0 : passes, hmax, unique ? " unique" : "");
+                    use_table      ? "bitmap-naming"
+                    : parent_order ? "parent-order"
+                    : (km == KM_U32 ? "sort-u32" : km == KM_U64 ? "sort-u64" : "sort-2stage"),
+                    use_table || parent_order ? 0 : passes, hmax, unique ? " unique" : "");
         if (unique && use_table)
             LOR_LAUNCH("k_sa12_from_names", 12.0 * d.m, s,
                        hipLaunchKernelGGL(k_sa12_from_names, dim3(g_el), dim3(kBlock), 0, s, R, d.m, sa12));
@@ -1041,7 +1472,8 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     ar.release(mark_tmp);
 
     if (!unique) {
-        LOR_TRY(dc3_level<int32_t>(R, d.m, hmax, sa12, ar, hdr, s, depth + 1));
+        // the child reads this level's sorted order (sa12) and names (keep) before its merge writes sa12
+        LOR_TRY(dc3_level<int32_t>(R, d.m, hmax, sa12, ar, hdr, s, depth + 1, keep));
         // rank12[sa12[r]] = r + 1, as a bucketed scatter
         const size_t mk = ar.mark();
         uint32_t *tb[4], *cr;
@@ -1059,10 +1491,11 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     LOR_TAKE(ar, uint32_t, d.n0, keys0);
     LOR_TAKE(ar, uint32_t, d.n0, vals0);
     if (run)
-        LOR_LAUNCH("k_records", (double)(d.n0 + 1) * (sizeof(Rec<CH>) + 12) + (double)n * sizeof(CH) + 8.0 * d.n0,
+        LOR_LAUNCH("k_records",
+                   (double)(d.n0 + 1) * (sizeof(Rec<CH>) + 12) + (double)n * sizeof(CH) + (parent_order ? 0.0 : 8.0 * d.n0),
                    s,
                    hipLaunchKernelGGL(k_records<CH>, dim3(grid_for(d.n0 + 1)), dim3(kBlock), 0, s, t, d, rank12,
-                                      rec, keys0, vals0));
+                                      rec, parent_order ? nullptr : keys0, parent_order ? nullptr : vals0));
 
     // ---- Step 2: mod-0 suffixes
     LOR_TAKE(ar, uint32_t, d.n0, keys1);
@@ -1077,21 +1510,81 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     uint32_t *split, *csplit;   // sized for the smallest merge tile, so the workspace does not depend on the plan
     LOR_TAKE(ar, uint32_t, (size_t)div_up(n, kBlock * 4) + 2, split);
     LOR_TAKE(ar, uint32_t, (size_t)div_up(n, kBlock * 4 * kCoarse) + 2, csplit);
-    if (run) {
-        // first symbols of the mod-0 suffixes in sample order, into R (its
-        // ranks were consumed by k_records, which also wrote these pairs)
-        uint32_t *const tmp4[4] = {keys1, vals1, sc0, sc1};
-        LOR_TRY(bucketed_scatter(R, d.m, keys0, vals0, 0, d.n0, tmp4, counts2, s, false));
-        const uint32_t G = scan_groups(d.m);
-        LOR_LAUNCH("k_ns_count", (double)d.m * 4, s,
-                   hipLaunchKernelGGL(k_ns_count, dim3(G), dim3(kBlock), 0, s, sa12, d, G, gcount2));
-        LOR_TRY(scan_block_totals(gcount2, G, hdr + 2, s));
-        LOR_LAUNCH("k_ns_write", (double)d.m * 4 + (double)d.n0 * 12, s,
-                   hipLaunchKernelGGL(k_ns_write, dim3(G), dim3(kBlock), 0, s, R, sa12, d, G, gcount2, keys0,
+    // Step 2 from the parent's order (see k_po0_write): the subset of mod-0
+    // positions whose symbol repeats among them is sorted by (symbol, rank of
+    // the next suffix) and put back into its slots.
+    const uint32_t ms0_cap = min(d.n0, d.n / 4u + 2u);
+    uint32_t *sub0_slot = nullptr, *sub0_pos = nullptr;
+    if (parent_order || !run) {
+        LOR_TAKE(ar, uint32_t, ms0_cap, sub0_slot);
+        LOR_TAKE(ar, uint32_t, ms0_cap, sub0_pos);
+    }
+    if (parent_order) {
+        const uint32_t Gn = scan_groups(d.n), G0 = scan_groups(d.n0);
+        LOR_LAUNCH("k_po_count", 4.0 * d.n, s,
+                   hipLaunchKernelGGL(k_po0_count, dim3(Gn), dim3(kBlock), 0, s, sa, d.n, Gn, gcount2));
+        LOR_TRY(scan_block_totals(gcount2, Gn, nullptr, s));
+        LOR_LAUNCH("k_po_write", 4.0 * d.n + 8.0 * d.n0, s,   // NS read for the kept third only
+                   hipLaunchKernelGGL(k_po0_write, dim3(Gn), dim3(kBlock), 0, s, sa, pnames, d, Gn, gcount2, keys0,
                                       vals0));
-        bool alt;
-        LOR_TRY(radix_sort<uint32_t>(keys0, vals0, keys1, vals1, d.n0, 0, b, counts2, s, &alt));
-        const uint32_t *A = alt ? vals1 : vals0;
+        LOR_LAUNCH("k_po_runs_count", 4.0 * d.n0, s,
+                   hipLaunchKernelGGL(k_po_runs_count, dim3(G0), dim3(kBlock), 0, s, vals0, d.n0, G0, gcount2));
+        LOR_TRY(scan_block_totals(gcount2, G0, hdr + 2, s));
+        LOR_LAUNCH("k_po_runs_write", 8.0 * d.n0, s,
+                   hipLaunchKernelGGL(k_po_runs_write, dim3(G0), dim3(kBlock), 0, s, vals0,
+                                      reinterpret_cast<const int32_t *>(keys0), d.n0, G0, gcount2, ms0_cap, sub0_slot,
+                                      sub0_pos, (uint32_t *)nullptr));
+    }
+    uint32_t ms0 = 0;
+    if (parent_order) {
+        LOR_TRY(decided_count(hdr, 2, &ms0, s));
+        if (ms0 > ms0_cap) {
+            set_error("internal: %u of %u mod-0 suffixes share a first symbol (at most %u expected)", ms0, d.n0,
+                      ms0_cap);
+            return LOR_EINVAL;
+        }
+    } else if (!run) {
+        ms0 = ms0_cap;
+    }
+    if (ms0 > 0) {
+        uint64_t *zk0, *zk1;
+        uint32_t *zv0, *zv1, *zcnt;
+        LOR_TAKE(ar, uint64_t, ms0, zk0);
+        LOR_TAKE(ar, uint64_t, ms0, zk1);
+        LOR_TAKE(ar, uint32_t, ms0, zv0);
+        LOR_TAKE(ar, uint32_t, ms0, zv1);
+        LOR_TAKE(ar, uint32_t, radix_counts_words(ms0), zcnt);
+        if (run) {
+            LOR_LAUNCH("k_po_keys", 20.0 * ms0, s,
+                       hipLaunchKernelGGL(k_po0_keys, dim3(grid_for(ms0)), dim3(kBlock), 0, s, vals0, sub0_slot,
+                                          sub0_pos, ms0, rank12, d, zk0, zv0));
+            bool zalt;
+            LOR_TRY(radix_sort<uint64_t>(zk0, zv0, zk1, zv1, ms0, 0, 32 + b, zcnt, s, &zalt));
+            LOR_LAUNCH("k_po_place", 12.0 * ms0, s,
+                       hipLaunchKernelGGL(k_po0_place, dim3(grid_for(ms0)), dim3(kBlock), 0, s, zalt ? zv1 : zv0,
+                                          sub0_slot, ms0, d.n0, keys0));
+        }
+    }
+    if (run) {
+        const uint32_t *A;
+        if (parent_order) {
+            A = keys0;
+        } else {
+            // first symbols of the mod-0 suffixes in sample order, into R (its
+            // ranks were consumed by k_records, which also wrote these pairs)
+            uint32_t *const tmp4[4] = {keys1, vals1, sc0, sc1};
+            LOR_TRY(bucketed_scatter(R, d.m, keys0, vals0, 0, d.n0, tmp4, counts2, s, false));
+            const uint32_t G = scan_groups(d.m);
+            LOR_LAUNCH("k_ns_count", (double)d.m * 4, s,
+                       hipLaunchKernelGGL(k_ns_count, dim3(G), dim3(kBlock), 0, s, sa12, d, G, gcount2));
+            LOR_TRY(scan_block_totals(gcount2, G, hdr + 2, s));
+            LOR_LAUNCH("k_ns_write", (double)d.m * 4 + (double)d.n0 * 12, s,
+                       hipLaunchKernelGGL(k_ns_write, dim3(G), dim3(kBlock), 0, s, R, sa12, d, G, gcount2, keys0,
+                                          vals0));
+            bool alt;
+            LOR_TRY(radix_sort<uint32_t>(keys0, vals0, keys1, vals1, d.n0, 0, b, counts2, s, &alt));
+            A = alt ? vals1 : vals0;
+        }
         const int32_t *B = sa12 + d.dummy;
         const uint32_t nB = d.m - d.dummy;
         const uint32_t cparts = div_up(parts, kCoarse);
@@ -1129,17 +1622,17 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
 
 lor_status dc3_u8(const uint8_t *text, uint32_t n, uint32_t alphabet, int32_t *sa, Arena &ar, uint32_t *hdr,
                   hipStream_t s) {
-    return dc3_level<uint8_t>(text, n, alphabet, sa, ar, hdr, s, 0);
+    return dc3_level<uint8_t>(text, n, alphabet, sa, ar, hdr, s, 0, nullptr);
 }
 
 lor_status dc3_i32(const int32_t *text, uint32_t n, uint32_t alphabet, int32_t *sa, Arena &ar, uint32_t *hdr,
                    hipStream_t s) {
-    return dc3_level<int32_t>(text, n, alphabet, sa, ar, hdr, s, 0);
+    return dc3_level<int32_t>(text, n, alphabet, sa, ar, hdr, s, 0, nullptr);
 }
 
 lor_status dc3_u16(const uint16_t *text, uint32_t n, uint32_t alphabet, int32_t *sa, Arena &ar, uint32_t *hdr,
                    hipStream_t s) {
-    return dc3_level<uint16_t>(text, n, alphabet, sa, ar, hdr, s, 0);
+    return dc3_level<uint16_t>(text, n, alphabet, sa, ar, hdr, s, 0, nullptr);
 }
 
 void set_decision_tape(DecisionTape *tape) { t_tape = tape; }
@@ -1148,7 +1641,7 @@ DecisionTape *decision_tape() { return t_tape; }
 size_t dc3_workspace_bound(uint64_t n) {
     Arena ar;   // measuring
     if (n == 0) return 0;
-    dc3_level<int32_t>(nullptr, (uint32_t)n, 0x7fffffffu, nullptr, ar, nullptr, nullptr, 0);
+    dc3_level<int32_t>(nullptr, (uint32_t)n, 0x7fffffffu, nullptr, ar, nullptr, nullptr, 0, nullptr);
     return ar.high + 4096;
 }
 
