@@ -4,8 +4,11 @@ Every function has the name of the C entry point it calls and runs that
 entry point on torch's current HIP stream (or the stream passed in). Device
 buffers are torch tensors on a ROCm device; the library itself never
 allocates device memory, so workspaces and outputs are allocated here with
-torch when the caller does not pass them. There is no fallback: if the built
-library is missing, loading raises.
+torch when the caller does not pass them. When a stream is passed, those
+allocations are made on that stream (torch's caching allocator then hands a
+freed workspace only to later work of the same stream, which runs after the
+kernels that used it). There is no fallback: if the built library is
+missing, loading raises.
 
 Unsigned 32-bit keys travel in torch.int32 tensors and 64-bit keys in
 torch.int64 tensors (same bits).
@@ -13,6 +16,8 @@ torch.int64 tensors (same bits).
 from __future__ import annotations
 
 import ctypes
+import functools
+import inspect
 import os
 import re
 
@@ -135,6 +140,23 @@ def _check(fn: str, status: int):
         raise LorError(fn, status, lib().lor_last_error().decode())
 
 
+def _on_stream(fn):
+    """Run `fn` with the `stream` keyword argument (when given) as torch's
+    current stream, so that the workspaces and outputs it allocates belong to
+    the stream its kernels are enqueued on."""
+    sig = inspect.signature(fn)
+
+    @functools.wraps(fn)
+    def wrapper(*args, **kwargs):
+        stream = sig.bind_partial(*args, **kwargs).arguments.get("stream")
+        if stream is None:
+            return fn(*args, **kwargs)
+        import torch
+        with torch.cuda.stream(stream):
+            return fn(*args, **kwargs)
+    return wrapper
+
+
 def _stream(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -173,6 +195,7 @@ def lor_build_sa_workspace(total_bases: int, num_seqs: int) -> int:
     return int(lib().lor_build_sa_workspace(total_bases, num_seqs))
 
 
+@_on_stream
 def lor_build_sa(seqs, offsets, joined_out=None, sa_out=None, ws=None, stream=None):
     """Suffix array of the separator-joined text. Returns (sa, joined)."""
     import torch
@@ -199,6 +222,7 @@ def lor_suffix_array_workspace(n: int) -> int:
     return int(lib().lor_suffix_array_workspace(n))
 
 
+@_on_stream
 def lor_suffix_array_i32(text, alphabet_max: int, sa_out=None, ws=None, stream=None):
     """DC3 suffix array of an int32 text with symbols in 1..alphabet_max."""
     import torch
@@ -221,6 +245,7 @@ def lor_build_lcp_workspace(n: int) -> int:
     return int(lib().lor_build_lcp_workspace(n))
 
 
+@_on_stream
 def lor_build_lcp(text, sa, lcp_out=None, isa_out=None, want_isa=False, ws=None, stream=None):
     """LCP (and optionally ISA) of `text` given its suffix array. Returns (lcp, isa|None)."""
     import torch
@@ -273,6 +298,7 @@ def lor_rmq_compact_bytes(n: int) -> int:
     return int(lib().lor_rmq_compact_bytes(n))
 
 
+@_on_stream
 def lor_rmq_build(lcp, table=None, stream=None) -> Rmq:
     import torch
     n = lcp.numel()
@@ -287,6 +313,7 @@ def lor_rmq_build(lcp, table=None, stream=None) -> Rmq:
     return Rmq(h, table)
 
 
+@_on_stream
 def lor_rmq_compact_build(lcp, table=None, stream=None) -> Rmq:
     import torch
     n = lcp.numel()
@@ -301,6 +328,7 @@ def lor_rmq_compact_build(lcp, table=None, stream=None) -> Rmq:
     return Rmq(h, table)
 
 
+@_on_stream
 def lor_rmq_query(rmq: Rmq, lcp, isa, mode: int, qi, qj, min_out=None, argmin_out=None, want_argmin=False,
                   stream=None):
     """mode 0: ranges [qi, qj] of LCP; mode 1: lcp of suffix pairs (qi, qj). Returns (min, argmin|None)."""
@@ -324,6 +352,7 @@ def lor_longest_overlap_workspace(n: int, num_seqs: int) -> int:
     return int(lib().lor_longest_overlap_workspace(n, num_seqs))
 
 
+@_on_stream
 def lor_longest_overlap(sa, lcp, offsets, ws=None, stream=None) -> tuple:
     """(length, seq_p, off_p, seq_q, off_q) of the longest region shared by two sequences."""
     o = _offsets(offsets)
@@ -344,6 +373,7 @@ def lor_longest_overlap_batched_workspace(total_bases: int, num_pairs: int) -> i
     return int(lib().lor_longest_overlap_batched_workspace(total_bases, num_pairs))
 
 
+@_on_stream
 def lor_longest_overlap_batched(seqs, offsets, out=None, ws=None, stream=None, plan=None):
     """Longest overlap of every pair (sequences 2p, 2p+1). Returns an int64
     device tensor [num_pairs, 4] of (length, off_p, off_q, seq_p | seq_q << 8)
@@ -371,6 +401,7 @@ def lor_longest_overlap_ref_workspace(total_bases: int, num_queries: int) -> int
     return int(lib().lor_longest_overlap_ref_workspace(total_bases, num_queries))
 
 
+@_on_stream
 def lor_longest_overlap_ref(seqs, offsets, out=None, ws=None, stream=None):
     """Longest substring every query (sequences 1..Q) shares with the
     reference (sequence 0). Returns the device lor_overlap records as bytes
@@ -394,6 +425,7 @@ def lor_overlap_matrix_workspace(n: int, num_seqs: int) -> int:
     return int(lib().lor_overlap_matrix_workspace(n, num_seqs))
 
 
+@_on_stream
 def lor_overlap_matrix(sa, lcp, offsets, out=None, ws=None, stream=None):
     """All-pairs longest overlap of the sequences of one joined text: device
     lor_overlap records, k x k, row a / column b (see records_to_tuples)."""
@@ -458,10 +490,11 @@ def lor_longest_overlap_batched_graph_create(seqs, offsets, stream, out=None, ws
         raise ValueError("offsets: need int64[2 * num_pairs + 1]")
     P = (o.size - 1) // 2
     _need(seqs, torch.uint8, int(o[-1]), "seqs")
-    if out is None:
-        out = torch.empty(P * ctypes.sizeof(lor_overlap), dtype=torch.uint8, device=seqs.device)
-    nbytes = lor_longest_overlap_batched_workspace(int(o[-1]), P)
-    ws = _workspace(nbytes, seqs.device, ws)
+    with torch.cuda.stream(stream):   # the graph's buffers belong to the stream it replays on
+        if out is None:
+            out = torch.empty(P * ctypes.sizeof(lor_overlap), dtype=torch.uint8, device=seqs.device)
+        nbytes = lor_longest_overlap_batched_workspace(int(o[-1]), P)
+        ws = _workspace(nbytes, seqs.device, ws)
     pl = None
     if plan is not None:
         pl = ctypes.byref(plan if isinstance(plan, lor_plan) else make_plan(**plan))
@@ -500,11 +533,13 @@ def _sort_pairs(fn, key_bytes, keys, vals, bit_lo, bit_hi, ws, stream):
     return keys, vals
 
 
+@_on_stream
 def lor_sort_pairs_u32(keys, vals, bit_lo=0, bit_hi=32, ws=None, stream=None):
     """Stable in-place sort of (keys: int32 bits, vals: int32) by key bits [bit_lo, bit_hi)."""
     return _sort_pairs("lor_sort_pairs_u32", 4, keys, vals, bit_lo, bit_hi, ws, stream)
 
 
+@_on_stream
 def lor_sort_pairs_u64(keys, vals, bit_lo=0, bit_hi=64, ws=None, stream=None):
     """Stable in-place sort of (keys: int64 bits, vals: int32) by key bits [bit_lo, bit_hi)."""
     return _sort_pairs("lor_sort_pairs_u64", 8, keys, vals, bit_lo, bit_hi, ws, stream)
@@ -567,6 +602,7 @@ def lor_timing_read() -> dict:
 
 # ------------------------------------------------------------- whole path
 
+@_on_stream
 def longest_overlap_region(seqs, offsets, want_isa=False, stream=None):
     """Join -> SA -> LCP -> overlap on the device. Returns dict with sa, joined, lcp, isa, overlap."""
     sa, joined = lor_build_sa(seqs, offsets, stream=stream)
