@@ -283,6 +283,18 @@ lor_status lor_sort_pairs_u32(uint32_t *keys, uint32_t *vals, int64_t n, int32_t
 lor_status lor_sort_pairs_u64(uint64_t *keys, uint32_t *vals, int64_t n, int32_t bit_lo, int32_t bit_hi,
                               void *ws, size_t ws_bytes, void *hip_stream);
 
+/* The same stable sort (u32 keys) with the design of Section IV's kernel
+ * (Alg. 1) and the chunk merge described after it, kept to measure that
+ * design on this GPU: each workgroup sorts a chunk of 2048 keys in LDS with
+ * one split per key bit (E = bit xor 1, F = exclusive prefix sum of E,
+ * totalFalse = E[n-1] + F[n-1], destination F[i] for a 0 bit and
+ * i - F[i] + totalFalse for a 1 bit; the prefix sum of the split example of
+ * Section IV is read as F = {0,0,1,1,1}), then runs of sorted chunks are
+ * merged pairwise (ties from the left run) until one run remains. Same
+ * arguments, workspace size and result as lor_sort_pairs_u32. */
+lor_status lor_sort_pairs_split_u32(uint32_t *keys, uint32_t *vals, int64_t n, int32_t bit_lo, int32_t bit_hi,
+                                    void *ws, size_t ws_bytes, void *hip_stream);
+
 /* --------------------------------------------------------------- tuning
  * Tuning knobs of the kernels, chosen by the autotuner
  * (paper_1404_3448_amd/autotune.py). A plan changes speed, never results.

@@ -729,6 +729,27 @@ lor_status lor_sort_pairs_u64(uint64_t *keys, uint32_t *vals, int64_t n, int32_t
     return sort_pairs<uint64_t>(keys, vals, n, bit_lo, bit_hi, ws, ws_bytes, hip_stream);
 }
 
+lor_status lor_sort_pairs_split_u32(uint32_t *keys, uint32_t *vals, int64_t n, int32_t bit_lo, int32_t bit_hi,
+                                    void *ws, size_t ws_bytes, void *hip_stream) {
+    if (n < 0 || n > INT32_MAX || bit_lo < 0 || bit_hi > 32 || bit_lo >= bit_hi || (n > 0 && (!keys || !vals))) {
+        set_error("invalid sort arguments");
+        return LOR_EINVAL;
+    }
+    LOR_TRY(check_ws(ws, ws_bytes, lor_sort_pairs_workspace(n, 4)));
+    hipStream_t s = (hipStream_t)hip_stream;
+    Arena ar = arena_after_header(ws, ws_bytes);
+    uint32_t *k1, *v1;
+    LOR_TAKE(ar, uint32_t, (size_t)n, k1);
+    LOR_TAKE(ar, uint32_t, (size_t)n, v1);
+    bool alt = false;
+    LOR_TRY(split_radix_sort(keys, vals, k1, v1, (uint32_t)n, bit_lo, bit_hi, s, &alt));
+    if (alt) {
+        LOR_HIP(hipMemcpyAsync(keys, k1, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+        LOR_HIP(hipMemcpyAsync(vals, v1, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+    }
+    return LOR_OK;
+}
+
 void lor_plan_default(lor_plan *out) {
     if (!out) return;
     *out = lor_plan{1, 8, 16, 8, 8, 128};

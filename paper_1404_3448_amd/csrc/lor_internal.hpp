@@ -178,6 +178,11 @@ template <typename K>
 lor_status radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, uint32_t n, int bit_lo,
                       int bit_hi, uint32_t *counts, hipStream_t s, bool *in_alt);
 int radix_passes(int bit_lo, int bit_hi);
+// The paper's radix-sort design (one split per key bit inside every chunk,
+// then pairwise merges of sorted chunks), u32 keys and values; the sorted
+// data end in (k1, v1) when *in_alt is set.
+lor_status split_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, uint32_t n, int bit_lo,
+                            int bit_hi, hipStream_t s, bool *in_alt);
 
 // ------------------------------------------------------ bucketed scatter
 // dst[idx[i]] = val[i] for i < n (idx a permutation into dst[0..dst_n) or a

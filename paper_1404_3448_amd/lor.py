@@ -112,6 +112,7 @@ def lib():
         "lor_sort_pairs_workspace": ([I64, I32], SZ),
         "lor_sort_pairs_u32": ([P, P, I64, I32, I32, P, SZ, P], I32),
         "lor_sort_pairs_u64": ([P, P, I64, I32, I32, P, SZ, P], I32),
+        "lor_sort_pairs_split_u32": ([P, P, I64, I32, I32, P, SZ, P], I32),
         "lor_plan_default": ([ctypes.POINTER(lor_plan)], None),
         "lor_plan_get": ([ctypes.POINTER(lor_plan)], None),
         "lor_plan_set": ([ctypes.POINTER(lor_plan)], I32),
@@ -543,6 +544,13 @@ def lor_sort_pairs_u32(keys, vals, bit_lo=0, bit_hi=32, ws=None, stream=None):
 def lor_sort_pairs_u64(keys, vals, bit_lo=0, bit_hi=64, ws=None, stream=None):
     """Stable in-place sort of (keys: int64 bits, vals: int32) by key bits [bit_lo, bit_hi)."""
     return _sort_pairs("lor_sort_pairs_u64", 8, keys, vals, bit_lo, bit_hi, ws, stream)
+
+
+@_on_stream
+def lor_sort_pairs_split_u32(keys, vals, bit_lo=0, bit_hi=32, ws=None, stream=None):
+    """The same sort with the paper's design (per-chunk one-bit splits, then
+    pairwise merges of sorted chunks)."""
+    return _sort_pairs("lor_sort_pairs_split_u32", 4, keys, vals, bit_lo, bit_hi, ws, stream)
 
 
 # ----------------------------------------------------------------- plans
