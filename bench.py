@@ -9,10 +9,19 @@ tandem repeats over ~10% of each), joined length N = 1,073,741,840, with
 10,000,000 uniform (i, j) queries (seed 3). `value` is N / step time in
 Msuffixes/s for the whole step; the SA+LCP-only rate is reported beside it.
 
-After the timed steps, `batched` reports 4096 independent pairs (seed 4)
-through one batched call against a loop of the plain per-pair path,
-`serving` the continuous-batching loop under Poisson load (p50/p99), and
-`cpu_baseline` times the CPU oracle on a bounded sample of the same text.
+After the timed steps:
+* `end_to_end_with_h2d`: one step with the bases copied in from pinned host
+  memory first (never `value`);
+* `configs`: the 50k + 50k pair (latency, parity with the oracle's scan and
+  its O(nm) DP, oracle times) and the 8M + 8M pair with 20 planted mutated
+  segments (N / (t_SA + t_LCP), per-kernel rates, parity, rate with H2D);
+* `ref_queries` and `ref_queries_sweep`: one reference against 65,536 query
+  sequences, and against 512 ... 1,048,576 of them;
+* `batched`: 4096 independent pairs (seed 4) through one batched call
+  against a loop of the plain per-pair path, its HIP graph, a 64-pair batch
+  eager against its graph, and the oracle looped over a sample of the pairs;
+* `serving`: the continuous-batching loop under Poisson load (p50/p99);
+* `cpu_baseline`: the CPU oracle on a bounded sample of the same text.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -258,6 +267,211 @@ def bench_rmq_compact(lor, torch, lcp, isa, qi, qj, qout, N, nq, stages, dev) ->
             "identical_to_full_table": bool(torch.equal(cout, qout))}
 
 
+def _event_ms(torch, fn, reps: int) -> list:
+    """Per-call device time of fn() on the current stream (HIP events), after one untimed call."""
+    fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return out
+
+
+def bench_c1(lor, synth, torch) -> dict:
+    """50k + 50k uniform bases with one exact 500-base copy (seed 1): latency
+    of the whole path on resident input (join, SA, LCP, overlap), parity with
+    the oracle's SA-scan overlap and its O(nm) DP, and the oracle times."""
+    import oracle
+    w = synth.tiny_pair(seed=1, n=50_000, planted_len=500)
+    dev = torch.device("cuda:0")
+    d = torch.from_numpy(w.concat).to(dev)
+    N = w.joined_length
+    joined = torch.empty(N, dtype=torch.uint8, device=dev)
+    sa = torch.empty(N, dtype=torch.int32, device=dev)
+    lcp = torch.empty(N, dtype=torch.int32, device=dev)
+    ws_sa = torch.empty(lor.lor_build_sa_workspace(int(w.offsets[-1]), 2), dtype=torch.uint8, device=dev)
+    ws_lcp = torch.empty(lor.lor_build_lcp_workspace(N), dtype=torch.uint8, device=dev)
+    ws_ov = torch.empty(lor.lor_longest_overlap_workspace(N, 2), dtype=torch.uint8, device=dev)
+    res = {}
+
+    def path():
+        lor.lor_build_sa(d, w.offsets, joined_out=joined, sa_out=sa, ws=ws_sa)
+        lor.lor_build_lcp(joined, sa, lcp_out=lcp, ws=ws_lcp)
+        res["ov"] = lor.lor_longest_overlap(sa, lcp, w.offsets, ws=ws_ov)   # synchronises
+
+    path()
+    lat = []
+    for _ in range(20):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        path()
+        lat.append(1e6 * (time.perf_counter() - t))
+    ov = res["ov"]
+    t = time.perf_counter()
+    j = oracle.join(w.concat, w.offsets)
+    so = oracle.suffix_array(j, nthreads=1)
+    lo = oracle.lcp(j, so, nthreads=1)
+    ov_o = oracle.overlap(so, lo, w.offsets)
+    t_sa = time.perf_counter() - t
+    t = time.perf_counter()
+    dp = oracle.lcs_dp(w.seqs[0], w.seqs[1])
+    t_dp = time.perf_counter() - t
+    return {"workload": "50,000 + 50,000 uniform bases, one exact 500-base copy (seed 1)", "joined_length": N,
+            "latency_us_p50": round(float(np.median(lat)), 1), "latency_us_min": round(float(min(lat)), 1),
+            "overlap": list(ov), "equals_oracle_scan": ov == ov_o,
+            "equals_oracle_dp": (ov[0], ov[2], ov[4]) == dp,
+            "certified": oracle.certify(j, sa.cpu().numpy(), lcp.cpu().numpy()) == -1,
+            "oracle_sa_lcp_scan_one_core_s": round(t_sa, 3), "oracle_dp_s": round(t_dp, 3)}
+
+
+def bench_c2(lor, synth, torch, threads: int) -> dict:
+    """8M + 8M noncoding-like bases with 20 planted mutated segments (seed 2):
+    N / (t_SA + t_LCP), per-kernel rates, overlap parity with the oracle, and
+    the rate with the bases copied in from pinned host memory first."""
+    import oracle
+    w = synth.noncoding_pair(seed=2)
+    dev = torch.device("cuda:0")
+    N = w.joined_length
+    host = torch.from_numpy(w.concat).pin_memory()
+    d = torch.empty_like(host, device=dev)
+    d.copy_(host)
+    joined = torch.empty(N, dtype=torch.uint8, device=dev)
+    sa = torch.empty(N, dtype=torch.int32, device=dev)
+    lcp = torch.empty(N, dtype=torch.int32, device=dev)
+    ws_sa = torch.empty(lor.lor_build_sa_workspace(int(w.offsets[-1]), 2), dtype=torch.uint8, device=dev)
+    ws_lcp = torch.empty(lor.lor_build_lcp_workspace(N), dtype=torch.uint8, device=dev)
+    ws_ov = torch.empty(lor.lor_longest_overlap_workspace(N, 2), dtype=torch.uint8, device=dev)
+    t_sa = _event_ms(torch, lambda: lor.lor_build_sa(d, w.offsets, joined_out=joined, sa_out=sa, ws=ws_sa), 5)
+    t_lcp = _event_ms(torch, lambda: lor.lor_build_lcp(joined, sa, lcp_out=lcp, ws=ws_lcp), 5)
+    t_h2d = _event_ms(torch, lambda: d.copy_(host, non_blocking=True), 5)
+    ms = float(np.median(t_sa)) + float(np.median(t_lcp))
+    lor.lor_timing_only(None)
+    lor.lor_timing_reset()
+    lor.lor_timing_enable(True)
+    lor.lor_build_sa(d, w.offsets, joined_out=joined, sa_out=sa, ws=ws_sa)
+    lor.lor_build_lcp(joined, sa, lcp_out=lcp, ws=ws_lcp)
+    torch.cuda.synchronize()
+    kern = lor.lor_timing_read()
+    lor.lor_timing_enable(False)
+    kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                   "alg_GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else 0.0}
+               for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])[:12]}
+    ov = lor.lor_longest_overlap(sa, lcp, w.offsets, ws=ws_ov)
+    t = time.perf_counter()
+    j = oracle.join(w.concat, w.offsets)
+    so = oracle.suffix_array(j, nthreads=threads)
+    lo = oracle.lcp(j, so, nthreads=threads)
+    ov_o = oracle.overlap(so, lo, w.offsets)
+    t_o = time.perf_counter() - t
+    same = bool(np.array_equal(sa.cpu().numpy(), so) and np.array_equal(lcp.cpu().numpy(), lo))
+    h2d = float(np.median(t_h2d))
+    return {"workload": "8,388,608 + 8,388,608 noncoding-like bases, 20 planted segments of 1k-10k bases with "
+                        "1% mutations (seed 2)", "joined_length": N,
+            "msuffixes_per_s": round(N / (ms * 1e-3) / 1e6, 1), "sa_ms": round(float(np.median(t_sa)), 3),
+            "lcp_ms": round(float(np.median(t_lcp)), 3), "h2d_ms": round(h2d, 3),
+            "msuffixes_per_s_with_h2d": round(N / ((ms + h2d) * 1e-3) / 1e6, 1),
+            "kernels": kernels, "overlap": list(ov), "sa_lcp_equal_oracle": same, "overlap_equals_oracle": ov == ov_o,
+            "oracle_s": round(t_o, 3), "oracle_threads": threads}
+
+
+def bench_c4_oracle_loop(synth, sample: int = 48) -> dict:
+    """The oracle looped over the first pairs of the 4096-pair batch (one
+    core): SA by comparison sort, LCP, overlap scan, per pair."""
+    import oracle
+    pairs = synth.batched_pairs()[:sample]
+    t = time.perf_counter()
+    bases = 0
+    for w in pairs:
+        j = oracle.join(w.concat, w.offsets)
+        so = oracle.suffix_array(j, nthreads=1)
+        oracle.overlap(so, oracle.lcp(j, so, nthreads=1), w.offsets)
+        bases += int(w.offsets[-1])
+    dt = time.perf_counter() - t
+    return {"pairs": sample, "bases": bases, "seconds": round(dt, 3), "pairs_per_s": round(sample / dt, 2),
+            "Mbases_per_s": round(bases / dt / 1e6, 3), "cores": 1}
+
+
+def bench_refq_sweep(lor, synth, torch, counts=(512, 4096, 32768, 262144, 1048576)) -> dict:
+    """lor_longest_overlap_ref over growing numbers of query sequences (the
+    NUMBER axis of Table V; Section V runs 512 and more queries per
+    reference): the same 4M-base reference, the first Q queries of one
+    generated list."""
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    w = synth.ref_queries(num_queries=max(counts))
+    gen_s = time.perf_counter() - t0
+    offs_all = w.offsets
+    d = torch.from_numpy(w.concat).to(dev)
+    out = {"reference_bases": int(w.seqs[0].size), "generated_s": round(gen_s, 1), "points": []}
+    for Q in counts:
+        offs = offs_all[: Q + 2]
+        total = int(offs[-1])
+        rec = torch.empty(Q * 32, dtype=torch.uint8, device=dev)
+        ws = torch.empty(lor.lor_longest_overlap_ref_workspace(total, Q), dtype=torch.uint8, device=dev)
+        sub = d[:total]
+        ts = []
+        for r in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            lor.lor_longest_overlap_ref(sub, offs, out=rec, ws=ws)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        dt = float(np.median(ts))
+        out["points"].append({"queries": Q, "bases": total, "ms": round(1e3 * dt, 3),
+                              "queries_per_s": round(Q / dt, 1), "Mbases_per_s": round(total / dt / 1e6, 1)})
+        del ws, rec
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_small_batch_graph(lor, synth, torch, pairs: int = 64, reps: int = 50) -> dict:
+    """A small batch (64 pairs of 1k-10k bases in total, seed 7): the batched
+    call eager against its captured HIP graph, where launch overhead matters."""
+    ws_pairs = synth.batched_pairs(seed=7, num_pairs=pairs, lo=1e3, hi=1e4)
+    seqs = [x for w in ws_pairs for x in w.seqs]
+    offs = np.concatenate([[0], np.cumsum([x.size for x in seqs])]).astype(np.int64)
+    dev = torch.device("cuda:0")
+    d = torch.from_numpy(np.concatenate(seqs)).to(dev)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        out = torch.empty(pairs * 32, dtype=torch.uint8, device=dev)
+        ws = torch.empty(lor.lor_longest_overlap_batched_workspace(int(offs[-1]), pairs), dtype=torch.uint8,
+                         device=dev)
+    side.wait_stream(torch.cuda.current_stream())
+    lor.lor_longest_overlap_batched(d, offs, out=out, ws=ws, stream=side)
+    eager = lor.records_to_tuples(out)
+    t = time.perf_counter()
+    for _ in range(reps):
+        lor.lor_longest_overlap_batched(d, offs, out=out, ws=ws, stream=side)
+    side.synchronize()
+    eager_s = (time.perf_counter() - t) / reps
+    g = lor.lor_longest_overlap_batched_graph_create(d, offs, side)
+    g.launch(side)
+    g.status(side)
+    t = time.perf_counter()
+    for _ in range(reps):          # one replay at a time, waited for (as the eager call waits)
+        g.launch(side)
+        g.status(side)
+    graph_s = (time.perf_counter() - t) / reps
+    t = time.perf_counter()
+    for _ in range(reps):          # replays queued back to back
+        g.launch(side)
+    g.status(side)
+    piped_s = (time.perf_counter() - t) / reps
+    same = lor.records_to_tuples(g.out) == eager
+    levels = g.levels
+    g.close()
+    return {"workload": f"{pairs} pairs, pair totals log-uniform in [1e3, 1e4], {int(offs[-1])} bases (seed 7)",
+            "eager_ms": round(1e3 * eager_s, 3), "graph_ms": round(1e3 * graph_s, 3),
+            "graph_queued_ms": round(1e3 * piped_s, 3), "graph_speedup": round(eager_s / graph_s, 2),
+            "graph_dc3_levels": levels, "identical": bool(same)}
+
+
 def bench_serving(seed: int = 5) -> dict:
     """Poisson requests (each sequence 1e4..4e6 bases, log-uniform; 30% keep
     state and send 10^4 follow-up queries after an exponential delay of mean
@@ -291,6 +505,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the overlap matrix, compact RMQ, radix ablation and reference-vs-queries runs")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 50k+50k and 8M+8M workloads, the query-count sweep and the oracle loops")
     ap.add_argument("--calibrate", action="store_true",
                     help="copy 1 GiB device-to-device first (reference for memory counters)")
     args = ap.parse_args()
@@ -327,10 +543,19 @@ def main():
     log(f"allocated {torch.cuda.memory_allocated() / 2**30:.1f} GiB on {torch.cuda.get_device_name(dev)}")
 
     if args.calibrate:
+        # kernels of known HBM bytes for the memory counters: a 1 GiB
+        # device-to-device copy (reads and writes 1 GiB), a 1 GiB fill (writes
+        # only) and a sum over 1 GiB of int32 (reads only)
         src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
+        torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
+        dst.fill_(3)
+        torch.cuda.synchronize()
+        total = int(dst.view(torch.int32).sum())
+        torch.cuda.synchronize()
+        log(f"calibration: copy, fill and sum over 1 GiB done ({total})")
         del src, dst
 
     names = ["sa", "lcp", "rmq_build", "queries", "overlap"]
@@ -395,6 +620,26 @@ def main():
         lor.lor_timing_enable(False)
         lor.lor_timing_only(None)
 
+    # End to end with the bases copied in from pinned host memory first (never `value`).
+    e2e = None
+    if not args.no_configs:
+        host = torch.from_numpy(w.concat).pin_memory()
+        ts = []
+        for _ in range(2):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record()
+            seqs.copy_(host, non_blocking=True)
+            ev[1].record()
+            step()
+            ev[2].record()
+            ev[2].synchronize()
+            ts.append((ev[0].elapsed_time(ev[1]), ev[0].elapsed_time(ev[2])))
+        h2d_ms, tot_ms = min(ts, key=lambda x: x[1])
+        e2e = {"h2d_ms": round(h2d_ms, 3), "step_with_h2d_ms": round(tot_ms, 3),
+               "msuffixes_per_s_with_h2d": round(N / (tot_ms * 1e-3) / 1e6, 3), "source": "pinned host memory"}
+        del host
+        log(f"end to end with H2D: {e2e}")
+
     ms_per_step = 1e3 * elapsed / args.steps
     value = N / (elapsed / args.steps) / 1e6
     stages = {k: round(v / args.steps, 3) for k, v in stage_ms.items()}
@@ -438,11 +683,32 @@ def main():
         refq = bench_ref_queries(lor, synth, torch)
         log(f"reference vs queries: {refq}")
 
+    configs = refq_sweep = None
+    if not args.no_configs:
+        threads = min(16, os.cpu_count() or 1)
+        log("50k + 50k ...")
+        configs = {"c1": bench_c1(lor, synth, torch)}
+        log(f"c1: {configs['c1']}")
+        log("8M + 8M ...")
+        configs["c2"] = bench_c2(lor, synth, torch, threads)
+        log(f"c2: {configs['c2']}")
+        torch.cuda.empty_cache()
+        log("reference vs queries, query-count sweep ...")
+        refq_sweep = bench_refq_sweep(lor, synth, torch)
+        log(f"refq sweep: {refq_sweep}")
+        torch.cuda.empty_cache()
+
     batched = None
     if not args.no_batched:
         log("batched vs plain loop ...")
         batched = bench_batched(lor, synth, torch)
         log(f"batched: {batched}")
+        torch.cuda.empty_cache()
+        batched["small_batch_graph"] = bench_small_batch_graph(lor, synth, torch)
+        log(f"small batch: {batched['small_batch_graph']}")
+        if not args.no_cpu_baseline:
+            batched["oracle_loop"] = bench_c4_oracle_loop(synth)
+            log(f"oracle loop over pairs: {batched['oracle_loop']}")
 
     serving = None
     if not args.no_serving:
@@ -487,6 +753,9 @@ def main():
         "overlap_matrix": matrix,
         "radix_ablation": abl,
         "ref_queries": refq,
+        "ref_queries_sweep": refq_sweep,
+        "configs": configs,
+        "end_to_end_with_h2d": e2e,
         "cpu_baseline": cpu,
         "paper_context": {"claim": "more than 20x over a serial CPU run (abstract, Section I)",
                           "hardware": "Intel Core i3-3110M host, GeForce 610M",
