@@ -11,7 +11,8 @@
  * Conventions for every entry point:
  *  - Device pointers point to memory of the current HIP device. The library
  *    never allocates device memory: the caller owns every buffer, including a
- *    workspace whose size the matching *_workspace() query returns.
+ *    workspace whose size the matching *_workspace() query returns (the one
+ *    exception is the fixed per-GPU array of lor_build_sa_static).
  *  - `hip_stream` is a hipStream_t (NULL = the null stream). Work is enqueued
  *    on it in order. Entry points whose result is a host value synchronise the
  *    stream before returning; the others return once work is enqueued, except
@@ -78,6 +79,24 @@ size_t lor_build_sa_workspace(int64_t total_bases, int32_t num_seqs);
 lor_status lor_build_sa(const uint8_t *seqs, const int64_t *offsets, int32_t num_seqs,
                         uint8_t *joined_out, int32_t *sa_out,
                         void *ws, size_t ws_bytes, void *hip_stream);
+
+/* Allocation-free form of lor_build_sa, for callers that cannot allocate
+ * device memory or pass a workspace (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc). Same inputs, outputs and
+ * results as lor_build_sa; the workspace is a fixed device array inside the
+ * library, LOR_STATIC_SCRATCH_BYTES (64 MiB) on every GPU the library runs
+ * on, held from the first call on that GPU until the process ends. The call
+ * itself allocates nothing (no hipMalloc, no events).
+ * joined_out may be NULL (the joined text then also lives in the array).
+ * Returns LOR_ETOOLARGE, before any GPU work, when lor_build_sa_workspace
+ * (or, with joined_out given, that less the joined text) exceeds
+ * LOR_STATIC_SCRATCH_BYTES: beyond about 1.8M joined symbols.
+ * hip_stream must belong to the current device. Every call on one GPU
+ * shares that GPU's array and leaves its contents behind: calls that overlap
+ * on one GPU (from other streams or threads) race and must be serialised. */
+#define LOR_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+lor_status lor_build_sa_static(const uint8_t *seqs, const int64_t *offsets, int32_t num_seqs,
+                               uint8_t *joined_out, int32_t *sa_out, void *hip_stream);
 
 /* DC3 core on an integer text (Section III, Steps 1-3, recursion on the
  * text of triple names). text: device int32[n] with every symbol in

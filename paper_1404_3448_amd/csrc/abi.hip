@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <initializer_list>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -196,6 +197,38 @@ size_t sa_bytes(int64_t N, bool need_joined) {
     return b + dc3_workspace_bound((uint64_t)N);
 }
 
+// Workspace of lor_build_sa_static: one fixed array per GPU, shared by every
+// call on that GPU. In host code `scratch` only names the array; its device
+// address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kStaticScratchBytes = LOR_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`.
+lor_status static_scratch(void **out) {
+    int dev = -1;
+    LOR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d outside 0..%d", dev, kMaxDevices - 1);
+        return LOR_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress of the static workspace on device %d: %s", dev, hipGetErrorString(e));
+            return LOR_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LOR_OK;
+}
+
 }  // namespace
 
 namespace {
@@ -272,6 +305,26 @@ lor_status lor_build_sa(const uint8_t *seqs, const int64_t *offsets, int32_t num
     LOR_TRY(join_text(seqs, offsets, num_seqs, joined, hdr, s));
     // symbols are byte + 1: bases 1..4, separators 5..4+num_seqs
     return dc3_u8(joined, (uint32_t)N, 4u + (uint32_t)num_seqs, sa_out, ar, hdr, s);
+}
+
+lor_status lor_build_sa_static(const uint8_t *seqs, const int64_t *offsets, int32_t num_seqs, uint8_t *joined_out,
+                               int32_t *sa_out, void *hip_stream) {
+    int64_t N = 0;
+    LOR_TRY(check_offsets(offsets, num_seqs, &N));
+    const size_t need = sa_bytes(N, joined_out == nullptr);
+    if (need > kStaticScratchBytes) {
+        set_error("joined length %lld needs %zu workspace bytes; the static workspace holds %zu", (long long)N, need,
+                  kStaticScratchBytes);
+        return LOR_ETOOLARGE;
+    }
+    void *ws = nullptr;
+    LOR_TRY(static_scratch(&ws));
+    // no event timing inside: its events would be created on demand
+    const bool was = t_capturing;
+    set_capturing(true);
+    const lor_status st = lor_build_sa(seqs, offsets, num_seqs, joined_out, sa_out, ws, kStaticScratchBytes, hip_stream);
+    set_capturing(was);
+    return st;
 }
 
 size_t lor_suffix_array_workspace(int64_t n) {

@@ -87,6 +87,7 @@ def lib():
         "lor_version": ([], I32),
         "lor_build_sa_workspace": ([I64, I32], SZ),
         "lor_build_sa": ([P, P, I32, P, P, P, SZ, P], I32),
+        "lor_build_sa_static": ([P, P, I32, P, P, P], I32),
         "lor_suffix_array_workspace": ([I64], SZ),
         "lor_suffix_array_i32": ([P, I64, I32, P, P, SZ, P], I32),
         "lor_build_lcp_workspace": ([I64], SZ),
@@ -216,6 +217,26 @@ def lor_build_sa(seqs, offsets, joined_out=None, sa_out=None, ws=None, stream=No
     st = lib().lor_build_sa(_ptr(seqs), o.ctypes.data_as(ctypes.c_void_p), k, _ptr(joined_out), _ptr(sa_out),
                             _ptr(ws), ws.numel() * ws.element_size(), _stream(stream))
     _check("lor_build_sa", st)
+    return sa_out[:N], joined_out[:N]
+
+
+STATIC_SCRATCH_BYTES = 64 << 20   # LOR_STATIC_SCRATCH_BYTES in include/lor.h
+
+
+@_on_stream
+def lor_build_sa_static(seqs, offsets, joined_out, sa_out, stream=None):
+    """lor_build_sa with the library's fixed per-GPU workspace: the caller
+    passes the outputs and nothing is allocated. Returns (sa, joined)."""
+    import torch
+    o = _offsets(offsets)
+    k = o.size - 1
+    N = int(o[-1]) + k
+    _need(seqs, torch.uint8, int(o[-1]), "seqs")
+    _need(joined_out, torch.uint8, N, "joined_out")
+    _need(sa_out, torch.int32, N, "sa_out")
+    st = lib().lor_build_sa_static(_ptr(seqs), o.ctypes.data_as(ctypes.c_void_p), k, _ptr(joined_out),
+                                   _ptr(sa_out), _stream(stream))
+    _check("lor_build_sa_static", st)
     return sa_out[:N], joined_out[:N]
 
 

@@ -177,3 +177,27 @@ def test_matrix_argument_errors(L):
     assert L.lor_overlap_matrix(FAKE, FAKE, 11, op, 2, None, FAKE, ws, None) == lor.LOR_EINVAL
     assert L.lor_overlap_matrix(FAKE, FAKE, 11, op, 2, FAKE, FAKE, ws - 1, None) == lor.LOR_EWORKSPACE
     assert lor.lor_overlap_matrix_workspace(11, 252) == 0
+
+
+def test_build_sa_static_size_and_argument_errors(L):
+    import re
+    with open(lor.HEADER_PATH) as f:
+        m = re.search(r"#define LOR_STATIC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", f.read())
+    assert m and int(m.group(1)) << int(m.group(2)) == lor.STATIC_SCRATCH_BYTES
+    o, op = offsets(0, 5, 9)
+    assert L.lor_build_sa_static(FAKE, op, 0, None, FAKE, None) == lor.LOR_EINVAL
+    bad, bp = offsets(0, 5, 3)
+    assert L.lor_build_sa_static(FAKE, bp, 2, None, FAKE, None) == lor.LOR_EINVAL
+    # the largest joined length whose workspace fits, with the joined text given
+    lo, hi = 1, 1 << 24
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        lo, hi = (mid, hi) if lor.lor_suffix_array_workspace(mid) <= lor.STATIC_SCRATCH_BYTES else (lo, mid - 1)
+    assert 1_500_000 < lo < 2_100_000
+    big, gp = offsets(0, lo - 1, lo - 1)   # joined length lo + 1: one symbol too many
+    assert L.lor_build_sa_static(FAKE, gp, 2, FAKE, FAKE, None) == lor.LOR_ETOOLARGE
+    assert b"static workspace" in L.lor_last_error()
+    fits, fp = offsets(0, lo - 2, lo - 2)
+    assert lor.lor_suffix_array_workspace(lo) <= lor.STATIC_SCRATCH_BYTES
+    # without joined_out the joined text also needs room in the array
+    assert L.lor_build_sa_static(FAKE, fp, 2, None, FAKE, None) == lor.LOR_ETOOLARGE
