@@ -221,6 +221,19 @@ lor_status lor_longest_overlap_batched(const uint8_t *seqs, const int64_t *offse
                                        const void *plan, lor_overlap *out_device,
                                        void *ws, size_t ws_bytes, void *hip_stream);
 
+/* The batched call that also keeps every pair's LCP and ISA, so that
+ * follow-up suffix-pair lcp queries (Section III: the lcp of two suffixes is
+ * the minimum LCP between their ranks) can be answered per pair. In the
+ * batch's tagged text pair p occupies positions, and its suffixes ranks,
+ * [s_p, s_p + n_p) with n_p = |A_p| + |B_p| + 2 and s_p the sum of n_q over
+ * q < p, in the pair's own order. lcp_out, isa_out: device int32[sum of n_p];
+ * lcp_out[s_p + r] is pair p's own LCP[r] (lor_build_lcp of its joined text
+ * A 4 B 5) and isa_out[s_p + x] - s_p its own ISA[x]. Workspace, arguments,
+ * records and synchronisation as lor_longest_overlap_batched. */
+lor_status lor_longest_overlap_batched_state(const uint8_t *seqs, const int64_t *offsets, int32_t num_pairs,
+                                             const void *plan, lor_overlap *out_device, int32_t *lcp_out,
+                                             int32_t *isa_out, void *ws, size_t ws_bytes, void *hip_stream);
+
 /* --------------------------------------------------- all-pairs overlap
  * The longest overlap region of every pair of different sequences of one
  * joined text (lor_build_sa's layout), from its SA and LCP: a num_seqs x

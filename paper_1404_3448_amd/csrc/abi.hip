@@ -592,6 +592,22 @@ lor_status lor_longest_overlap_batched(const uint8_t *seqs, const int64_t *offse
     return st;
 }
 
+lor_status lor_longest_overlap_batched_state(const uint8_t *seqs, const int64_t *offsets, int32_t num_pairs,
+                                             const void *plan, lor_overlap *out_device, int32_t *lcp_out,
+                                             int32_t *isa_out, void *ws, size_t ws_bytes, void *hip_stream) {
+    Plan call_plan{};
+    LOR_TRY(check_batched(seqs, offsets, num_pairs, plan, out_device, ws, ws_bytes, &call_plan));
+    if (!lcp_out || !isa_out) {
+        set_error("NULL lcp_out or isa_out");
+        return LOR_EINVAL;
+    }
+    if (plan) plan_set_thread(&call_plan);
+    const lor_status st = batch_overlap(seqs, offsets, (uint32_t)num_pairs, out_device, ws, ws_bytes,
+                                        (hipStream_t)hip_stream, lcp_out, isa_out);
+    plan_set_thread(nullptr);
+    return st;
+}
+
 lor_status lor_longest_overlap_batched_graph_create(const uint8_t *seqs, const int64_t *offsets, int32_t num_pairs,
                                                     const void *plan, lor_overlap *out_device, void *ws,
                                                     size_t ws_bytes, void *hip_stream, lor_batched_graph **graph) {

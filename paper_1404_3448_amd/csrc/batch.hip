@@ -477,7 +477,7 @@ uint64_t batch_tables(const int64_t *offsets, uint32_t P, int32_t *h_start, int3
 
 lor_status batch_overlap_run(const uint8_t *seqs, uint32_t P, uint64_t N, const int32_t *h_start,
                              const int32_t *h_alen, const int64_t *h_src, lor_overlap *out, void *ws,
-                             size_t ws_bytes, hipStream_t s) {
+                             size_t ws_bytes, hipStream_t s, int32_t *lcp_out, int32_t *isa_out) {
     Arena ar;
     ar.base = static_cast<char *>(ws);
     ar.cap = ws_bytes;
@@ -511,7 +511,8 @@ lor_status batch_overlap_run(const uint8_t *seqs, uint32_t P, uint64_t N, const 
                                   P, (uint32_t)N, in_end, text, hdr));
     LOR_TRY(dc3_u16(text, (uint32_t)N, 8u * (P - 1) + 6u, sa, ar, hdr, s));
     ar.release(phase);
-    LOR_TRY(lcp_build_u16(text, (uint32_t)N, sa, lcp, nullptr, ar, s));
+    if (lcp_out) lcp = lcp_out;   // the caller keeps the whole batch's LCP (and ISA)
+    LOR_TRY(lcp_build_u16(text, (uint32_t)N, sa, lcp, isa_out, ar, s));
     ar.release(phase);
 
     const uint32_t groups = div_up(N, kGroupRanks);
@@ -534,12 +535,13 @@ lor_status batch_overlap_run(const uint8_t *seqs, uint32_t P, uint64_t N, const 
 }
 
 lor_status batch_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t P, lor_overlap *out, void *ws,
-                         size_t ws_bytes, hipStream_t s) {
+                         size_t ws_bytes, hipStream_t s, int32_t *lcp_out, int32_t *isa_out) {
     std::vector<int32_t> h_start(P + 1), h_alen(P);
     std::vector<int64_t> h_src(2 * (size_t)P);
     const uint64_t N = batch_tables(offsets, P, h_start.data(), h_alen.data(), h_src.data());
     // DC3 reads back one word per level, which also orders the host copies
-    LOR_TRY(batch_overlap_run(seqs, P, N, h_start.data(), h_alen.data(), h_src.data(), out, ws, ws_bytes, s));
+    LOR_TRY(batch_overlap_run(seqs, P, N, h_start.data(), h_alen.data(), h_src.data(), out, ws, ws_bytes, s, lcp_out,
+                              isa_out));
     LOR_HIP(hipStreamSynchronize(s));   // the host tables must outlive their copies
     return LOR_OK;
 }

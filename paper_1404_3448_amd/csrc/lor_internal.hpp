@@ -277,15 +277,19 @@ size_t overlap_workspace(uint64_t n);
 // ------------------------------------------------------------ batched
 constexpr uint32_t kMaxPairs = 8191;   // tags 0..8190: 8 * tag + 6 fits 16 bits
 size_t batch_workspace(uint64_t total_bases, uint32_t num_pairs);
+// lcp_out / isa_out (nullable): the whole batch's LCP and ISA over the tagged
+// text instead of workspace scratch.
 lor_status batch_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t num_pairs, lor_overlap *out,
-                         void *ws, size_t ws_bytes, hipStream_t s);
+                         void *ws, size_t ws_bytes, hipStream_t s, int32_t *lcp_out = nullptr,
+                         int32_t *isa_out = nullptr);
 // The two halves of batch_overlap, for launch-sequence capture: host tables
 // of the pairs (returns the tagged length N), and the device work without
 // any final synchronisation (the host tables must outlive the copies).
 uint64_t batch_tables(const int64_t *offsets, uint32_t num_pairs, int32_t *h_start, int32_t *h_alen, int64_t *h_src);
 lor_status batch_overlap_run(const uint8_t *seqs, uint32_t num_pairs, uint64_t N, const int32_t *h_start,
                              const int32_t *h_alen, const int64_t *h_src, lor_overlap *out, void *ws,
-                             size_t ws_bytes, hipStream_t s);
+                             size_t ws_bytes, hipStream_t s, int32_t *lcp_out = nullptr,
+                             int32_t *isa_out = nullptr);
 // ---------------------------------------------- reference against queries
 size_t refq_workspace(uint64_t total_bases, uint32_t num_queries);
 lor_status refq_overlap(const uint8_t *seqs, const int64_t *offsets, uint32_t num_queries, lor_overlap *out,

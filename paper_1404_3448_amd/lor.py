@@ -101,6 +101,7 @@ def lib():
         "lor_longest_overlap": ([P, P, I64, P, I32, ctypes.POINTER(lor_overlap), P, SZ, P], I32),
         "lor_longest_overlap_batched_workspace": ([I64, I32], SZ),
         "lor_longest_overlap_batched": ([P, P, I32, P, P, P, SZ, P], I32),
+        "lor_longest_overlap_batched_state": ([P, P, I32, P, P, P, P, P, SZ, P], I32),
         "lor_longest_overlap_ref_workspace": ([I64, I32], SZ),
         "lor_overlap_matrix_workspace": ([I64, I32], SZ),
         "lor_overlap_matrix": ([P, P, I64, P, I32, P, P, SZ, P], I32),
@@ -417,6 +418,46 @@ def lor_longest_overlap_batched(seqs, offsets, out=None, ws=None, stream=None, p
                                            _ptr(ws), ws.numel() * ws.element_size(), _stream(stream))
     _check("lor_longest_overlap_batched", st)
     return out
+
+
+@_on_stream
+def lor_longest_overlap_batched_state(seqs, offsets, out=None, lcp_out=None, isa_out=None, ws=None, stream=None,
+                                      plan=None):
+    """lor_longest_overlap_batched that also returns the batch's LCP and ISA
+    over the tagged text: pair p's own LCP / ISA are lcp[s_p:s_p+n_p] and
+    isa[s_p:s_p+n_p] - s_p (pair_starts gives s_p). Returns (records, lcp, isa)."""
+    import torch
+    o = _offsets(offsets)
+    if (o.size - 1) % 2:
+        raise ValueError("offsets: need int64[2 * num_pairs + 1]")
+    P = (o.size - 1) // 2
+    N = int(o[-1]) + 2 * P
+    _need(seqs, torch.uint8, int(o[-1]), "seqs")
+    if out is None:
+        out = torch.empty(P * ctypes.sizeof(lor_overlap), dtype=torch.uint8, device=seqs.device)
+    if lcp_out is None:
+        lcp_out = torch.empty(N, dtype=torch.int32, device=seqs.device)
+    if isa_out is None:
+        isa_out = torch.empty(N, dtype=torch.int32, device=seqs.device)
+    _need(lcp_out, torch.int32, N, "lcp_out")
+    _need(isa_out, torch.int32, N, "isa_out")
+    nbytes = lor_longest_overlap_batched_workspace(int(o[-1]), P)
+    ws = _workspace(nbytes, seqs.device, ws)
+    pl = None
+    if plan is not None:
+        pl = ctypes.byref(plan if isinstance(plan, lor_plan) else make_plan(**plan))
+    st = lib().lor_longest_overlap_batched_state(_ptr(seqs), o.ctypes.data_as(ctypes.c_void_p), P, pl, _ptr(out),
+                                                 _ptr(lcp_out), _ptr(isa_out), _ptr(ws),
+                                                 ws.numel() * ws.element_size(), _stream(stream))
+    _check("lor_longest_overlap_batched_state", st)
+    return out, lcp_out[:N], isa_out[:N]
+
+
+def pair_starts(offsets) -> np.ndarray:
+    """s_p for every pair of a batched offsets array, and the total after the last."""
+    o = _offsets(offsets)
+    lens = o[2::2] - o[0:-1:2] + 2
+    return np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
 
 
 def lor_longest_overlap_ref_workspace(total_bases: int, num_queries: int) -> int:

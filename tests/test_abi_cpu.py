@@ -201,3 +201,15 @@ def test_build_sa_static_size_and_argument_errors(L):
     assert lor.lor_suffix_array_workspace(lo) <= lor.STATIC_SCRATCH_BYTES
     # without joined_out the joined text also needs room in the array
     assert L.lor_build_sa_static(FAKE, fp, 2, None, FAKE, None) == lor.LOR_ETOOLARGE
+
+
+def test_batched_state_argument_errors(L):
+    o, op = offsets(0, 5, 9)
+    ws = lor.lor_longest_overlap_batched_workspace(9, 1)
+    assert L.lor_longest_overlap_batched_state(FAKE, op, 1, None, FAKE, None, FAKE, FAKE, ws, None) == lor.LOR_EINVAL
+    assert L.lor_longest_overlap_batched_state(FAKE, op, 1, None, FAKE, FAKE, None, FAKE, ws, None) == lor.LOR_EINVAL
+    assert b"lcp_out" in L.lor_last_error()
+    assert L.lor_longest_overlap_batched_state(FAKE, op, 1, None, FAKE, FAKE, FAKE, FAKE, ws - 1, None) == \
+        lor.LOR_EWORKSPACE
+    assert L.lor_longest_overlap_batched_state(FAKE, op, 0, None, FAKE, FAKE, FAKE, FAKE, ws, None) == lor.LOR_EINVAL
+    assert list(lor.pair_starts([0, 5, 9, 9, 12])) == [0, 11, 16]

@@ -119,3 +119,36 @@ def test_batched_full_size_sampled():
         if L:
             assert (sp, sq) == (0, 1)
             assert np.array_equal(a[op:op + L], b[oq:oq + L])
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_batched_state_lcp_isa_per_pair(seed):
+    """lor_longest_overlap_batched_state: same records as the batched call, and
+    each pair's slice of the batch's LCP / ISA equals the oracle's LCP / ISA
+    of the pair's own joined text."""
+    rng = np.random.default_rng(900 + seed)
+    pairs = []
+    for _ in range(int(rng.integers(20, 60))):
+        la, lb = (int(x) for x in rng.integers(0, 3000, size=2))
+        a = synth.noncoding_like(rng, la) if la else np.zeros(0, np.uint8)
+        b = synth.noncoding_like(rng, lb) if lb else np.zeros(0, np.uint8)
+        if a.size > 100 and b.size > 100:
+            s = int(rng.integers(0, a.size - 60))
+            b = np.concatenate([b[:50], a[s:s + 60], b[50:]])
+        pairs.append((a, b))
+    d, offs = flat(pairs)
+    say("batched state", seed, len(pairs), int(offs[-1]))
+    out, lcp, isa = lor.lor_longest_overlap_batched_state(d, offs)
+    recs = lor.records_to_tuples(out)
+    assert recs == run_batched(pairs)
+    starts = lor.pair_starts(offs)
+    assert starts[-1] == lcp.numel()
+    lcp, isa = lcp.cpu().numpy(), isa.cpu().numpy()
+    for p, (a, b) in enumerate(pairs):
+        s0, s1 = int(starts[p]), int(starts[p + 1])
+        po = np.array([0, a.size, a.size + b.size], np.int64)
+        joined = oracle.join(np.concatenate([a, b]), po)
+        sa = oracle.suffix_array(joined)
+        assert np.array_equal(lcp[s0:s1], oracle.lcp(joined, sa)), p
+        assert np.array_equal(isa[s0:s1] - s0, oracle.isa(sa)), p
+        assert recs[p] == oracle.overlap(sa, oracle.lcp(joined, sa), po), p

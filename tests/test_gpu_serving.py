@@ -1,5 +1,6 @@
 """Serving on the GPU: every result (and follow-up answer) is the same served
-alone and in a concurrent mix, and equals the oracle."""
+alone and in a concurrent mix of batches, also when the HBM budget makes
+batches wait for memory, and equals the oracle."""
 import numpy as np
 import pytest
 
@@ -25,7 +26,7 @@ def alone(req):
 
 def test_alone_equals_mix():
     reqs = serve.make_requests(seed=5, count=80, qps=400.0, lo=1e3, hi=3e5, queries=2000, followup_mean=0.01)
-    srv = serve.Server(slots=4, small_bases=100_000, batch_max=16)
+    srv = serve.Server(slots=4, batch_max=16)
     stats = srv.run(reqs)
     assert stats["rejected"] == 0
     assert stats["batched_requests"] > 0 and stats["followups"] > 0
@@ -40,3 +41,17 @@ def test_alone_equals_mix():
         assert r.result == oracle.overlap(sa, oracle.lcp(joined, sa), r.offsets)
         if r.keep:
             assert np.array_equal(r.followup_result, oracle.pair_queries(joined, *r.followup))
+
+
+def test_alone_equals_mix_under_memory_pressure():
+    reqs = serve.make_requests(seed=8, count=40, qps=2000.0, lo=2e4, hi=2e5, queries=1000, followup_mean=0.005)
+    biggest = max(serve.Server._item_bytes("batch", [r]) for r in reqs)
+    srv = serve.Server(slots=4, batch_max=4, budget_bytes=int(2.5 * biggest))
+    stats = srv.run(reqs)
+    assert stats["rejected"] == 0 and stats["waits_for_memory"] > 0
+    assert srv.peak_in_use <= srv.budget and srv.in_use == 0
+    for r in reqs:
+        ov, fol = alone(r)
+        assert r.result == ov, r.rid
+        if r.keep:
+            assert np.array_equal(r.followup_result, fol), r.rid

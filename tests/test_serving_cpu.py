@@ -1,6 +1,6 @@
-"""Host logic of the serving loop with a fake runner (no GPU): admission by
-the HBM budget, mini-batching of small requests, rejection of requests that
-can never fit, follow-ups on resident state."""
+"""Host logic of the serving loop with a fake runner (no GPU): continuous
+batching, admission by the HBM budget (and waiting for memory), rejection of
+requests that can never fit, follow-ups on resident state."""
 import threading
 import time
 
@@ -25,8 +25,8 @@ class FakeRunner:
     def batch(self, reqs):
         with self.lock:
             self.calls.append(("batch", tuple(r.rid for r in reqs)))
-        time.sleep(0.002)
-        return [("batch", r.rid) for r in reqs]
+        time.sleep(1e-9 * sum(r.bases for r in reqs) + 0.002)
+        return [(("batch", r.rid), ({"rid": r.rid} if r.keep else None)) for r in reqs]
 
     def followup(self, req, state):
         assert state == {"rid": req.rid}
@@ -43,21 +43,39 @@ def mk(rid, na, nb, t, keep=False):
     return serve.Request(rid, a, b, t, keep, fol, 0.003 if keep else 0.0)
 
 
-def test_every_request_is_served_and_small_ones_batch():
-    reqs = [mk(i, 500 if i % 3 else 600_000, 400, 0.001 * i, keep=(i % 5 == 0)) for i in range(40)]
+def test_every_request_is_served_in_batches():
+    # bursts of 10 arrivals: more requests wait than there are free slots
+    reqs = [mk(i, 500 if i % 3 else 600_000, 400, 0.004 * (i // 10), keep=(i % 5 == 0)) for i in range(40)]
     runner = FakeRunner()
-    srv = serve.Server(runner=runner, slots=3, small_bases=100_000, batch_max=8, batch_wait=0.002)
+    srv = serve.Server(runner=runner, slots=3, batch_max=8, batch_bases=2_000_000)
     stats = srv.run(reqs)
     assert stats["requests"] == 40 and stats["rejected"] == 0
     for r in reqs:
-        kind = "plain" if (r.keep or r.bases > 100_000) else "batch"
-        assert r.result == (kind, r.rid)
+        assert r.result == ("batch", r.rid)
         assert r.t_result >= r.arrival
         if r.keep:
             assert np.all(r.followup_result == r.rid)
             assert r.t_followup_arrival >= r.t_result
-    assert stats["batched_requests"] == sum(1 for r in reqs if not r.keep and r.bases <= 100_000)
+    batches = [c[1] for c in runner.calls if c[0] == "batch"]
+    assert sorted(x for b in batches for x in b) == list(range(40))
+    assert max(len(b) for b in batches) > 1 and all(len(b) <= 8 for b in batches)
+    assert all(sum(reqs[x].bases for x in b) <= 2_000_000 or len(b) == 1 for b in batches)
+    for b in batches:                              # oldest first, in arrival order
+        assert list(b) == sorted(b)
+    assert stats["batched_requests"] == 40
     assert stats["followups"] == sum(r.keep for r in reqs)
+    assert srv.in_use == 0 and not srv.state
+
+
+def test_batches_wait_for_memory():
+    reqs = [mk(i, 40_000, 40_000, 0.0, keep=(i % 2 == 0)) for i in range(12)]
+    one = serve.Server._item_bytes("batch", reqs[:1])
+    runner = FakeRunner()
+    srv = serve.Server(runner=runner, budget_bytes=int(2.2 * one), slots=4, batch_max=3)
+    stats = srv.run(reqs)
+    assert stats["rejected"] == 0 and stats["waits_for_memory"] > 0
+    assert srv.peak_in_use <= srv.budget
+    assert all(r.result == ("batch", r.rid) for r in reqs)
     assert srv.in_use == 0 and not srv.state
 
 
