@@ -916,8 +916,16 @@ __global__ __launch_bounds__(kBlock) void k_flag_write(const uint32_t *__restric
     }
 }
 
+// Bit 31 set when symbol x = NS[r] of P's entry r occurs more than once in
+// the text (a neighbour in P has it too); symbols stay below 2^31.
+__device__ __forceinline__ uint32_t repeat_flag(const uint32_t *__restrict__ NS, uint32_t n, uint32_t r,
+                                                uint32_t x) {
+    return ((r > 0 && NS[r - 1] == x) || (r + 1 < n && NS[r + 1] == x)) ? 0x80000000u : 0u;
+}
+
 // Step 2 from the parent's order: the mod-0 positions of P, in order, with
-// their symbols (ties of the symbol then need the rank of the next suffix).
+// their symbols (ties of the symbol then need the rank of the next suffix),
+// flagged by repeat_flag for the merge.
 __global__ __launch_bounds__(kBlock) void k_po0_count(const int32_t *__restrict__ P, uint32_t n, uint32_t groups,
                                                       uint32_t *__restrict__ counts) {
     __shared__ uint32_t s_tmp[kBlock / kWave];
@@ -955,8 +963,9 @@ __global__ __launch_bounds__(kBlock) void k_po0_write(const int32_t *__restrict_
         for (int i = 0; i < kScanItems; ++i) {
             if (keep[i]) {
                 if (j < d.n0) {
+                    const uint32_t x = NS[r0 + i];
                     pos0[j] = p[i];
-                    sym0[j] = NS[r0 + i];
+                    sym0[j] = x | repeat_flag(NS, d.n, r0 + i, x);   // the flag only matters to the merge
                 }
                 ++j;
             }
@@ -988,18 +997,95 @@ __global__ __launch_bounds__(kBlock) void k_po0_place(const uint32_t *__restrict
     }
 }
 
+// Step 3 from the parent's order. Both merge inputs list their suffixes by
+// first symbol (A by Step 2, B as the sample order), in the same order of
+// symbols as the mod-0 and the sample entries of P. A suffix whose symbol
+// occurs once in the text differs in its first symbol from every other
+// suffix, so the merge places it by that symbol alone and needs its record
+// only when the symbol repeats. symA[j] / symB[k]: the symbol of A[j] /
+// B[k], with bit 31 set when the symbol occurs more than once in the text.
+// symB[k] = symbol of the k-th sample entry of P, flagged (counts: the
+// per-group sample counts of k_po_count, scanned). Tiles of P and NS (with
+// one entry of halo on each side) are staged in LDS.
+__global__ __launch_bounds__(kBlock) void k_msym_write(const int32_t *__restrict__ P, const uint32_t *__restrict__ NS,
+                                                       Dims d, uint32_t groups, const uint32_t *__restrict__ counts,
+                                                       uint32_t *__restrict__ symB) {
+    __shared__ uint32_t s_tmp[kBlock / kWave];
+    __shared__ __align__(16) uint32_t s_p[kScanTile];
+    __shared__ uint32_t s_ns[kScanTile + 2];
+    uint32_t t0, t1;
+    group_tiles(d.n, groups, blockIdx.x, &t0, &t1);
+    uint32_t base = counts[blockIdx.x];
+    const uint32_t nB = d.m - d.dummy;
+    for (uint32_t tile = t0; tile < t1; ++tile) {
+        const uint32_t g0 = tile * kScanTile;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint32_t l = i * kBlock + threadIdx.x, r = g0 + l;
+            s_p[l] = r < d.n ? (uint32_t)P[r] : 0u;   // 0: a mod-0 position, dropped
+            s_ns[l + 1] = r < d.n ? NS[r] : 0xffffffffu;
+        }
+        if (threadIdx.x == 0) s_ns[0] = g0 > 0 ? NS[g0 - 1] : 0xffffffffu;
+        if (threadIdx.x == 1) s_ns[kScanTile + 1] = g0 + kScanTile < d.n ? NS[g0 + kScanTile] : 0xffffffffu;
+        __syncthreads();
+        const uint32_t l0 = threadIdx.x * kScanItems;
+        uint32_t p[kScanItems], x[kScanItems];
+#pragma unroll
+        for (int h = 0; h < kScanItems / 4; ++h) {
+            const uint4 a = *reinterpret_cast<const uint4 *>(&s_p[l0 + 4 * h]);
+            p[4 * h] = a.x; p[4 * h + 1] = a.y; p[4 * h + 2] = a.z; p[4 * h + 3] = a.w;
+        }
+        uint32_t c = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint32_t l = l0 + i, v = s_ns[l + 1];
+            x[i] = v | ((s_ns[l] == v || s_ns[l + 2] == v) ? 0x80000000u : 0u);   // halo 0xffffffff matches no symbol
+            c += (p[i] % 3u) != 0u;
+        }
+        uint32_t tot;
+        uint32_t j = base + dev::block_exclusive_sum(c, s_tmp, &tot);
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            if ((p[i] % 3u) != 0u) {
+                if (j < nB) symB[j] = x[i];
+                ++j;
+            }
+        }
+        base += tot;
+        __syncthreads();   // the next tile reuses the LDS
+    }
+}
+
 // ------------------------------------------------------ Step 3: merge
 
 // A = mod-0 positions sorted (Step 2), B = sample order without the padding
 // position (R-indices). Merge path: the number of A elements among the first
 // `diag` outputs, by binary search inside [lo, hi] (which must hold it).
+// Key of merge input element j (symbols as above; sym == nullptr: always
+// from the record). pos() gives the element's text position.
+template <typename CH, typename POS>
+__device__ __forceinline__ Key4 merge_key(const Rec<CH> *rec, const uint32_t *sym, uint32_t j, POS pos) {
+    if (sym) {
+        const uint32_t x = sym[j];
+        if (!(x >> 31)) {
+            Key4 k;
+            k.c0 = x;   // unique first symbol: every comparison ends on it
+            k.c1 = k.r = k.r2cls = 0;
+            return k;
+        }
+    }
+    return key_of<CH>(rec, pos());
+}
+
 template <typename CH>
 __device__ __forceinline__ uint32_t merge_split(const Rec<CH> *rec, const uint32_t *A, const int32_t *B,
-                                                const Dims &d, uint32_t diag, uint32_t lo, uint32_t hi) {
+                                                const uint32_t *symA, const uint32_t *symB, const Dims &d,
+                                                uint32_t diag, uint32_t lo, uint32_t hi) {
     while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        const Key4 a = key_of<CH>(rec, min(A[mid], d.n - 1));
-        const Key4 b = key_of<CH>(rec, min(d.pos_of(min((uint32_t)B[diag - 1 - mid], d.m - 1)), d.n - 1));
+        const uint32_t mid = (lo + hi) >> 1, bj = diag - 1 - mid;
+        const Key4 a = merge_key<CH>(rec, symA, mid, [&] { return min(A[mid], d.n - 1); });
+        const Key4 b = merge_key<CH>(rec, symB, bj,
+                                     [&] { return min(d.pos_of(min((uint32_t)B[bj], d.m - 1)), d.n - 1); });
         if (!sample_less(b, a)) lo = mid + 1; else hi = mid;
     }
     return lo;
@@ -1018,6 +1104,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_partition(const Rec<CH> *__res
                                                             const int32_t *__restrict__ B, uint32_t nB,
                                                             Dims d, uint32_t parts, uint64_t tile,
                                                             const uint32_t *__restrict__ coarse, uint32_t cparts,
+                                                            const uint32_t *__restrict__ symA,
+                                                            const uint32_t *__restrict__ symB,
                                                             uint32_t *__restrict__ split) {
     const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
     if (p > parts) return;
@@ -1029,7 +1117,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_partition(const Rec<CH> *__res
         lo = min(max(lo0, coarse[c]), hi0);
         hi = max(min(hi0, coarse[min(c + 1, cparts)]), lo);
     }
-    split[p] = merge_split<CH>(rec, A, B, d, diag, lo, hi);
+    split[p] = merge_split<CH>(rec, A, B, symA, symB, d, diag, lo, hi);
 }
 
 template <typename CH, int ITEMS>
@@ -1037,7 +1125,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(const Rec<CH> *__restrict__ re
                                                   const uint32_t *__restrict__ A, uint32_t nA,
                                                   const int32_t *__restrict__ B, uint32_t nB, Dims d,
                                                   const uint32_t *__restrict__ split,
-                                                  int32_t *__restrict__ sa) {
+                                                  const uint32_t *__restrict__ symA,
+                                                  const uint32_t *__restrict__ symB, int32_t *__restrict__ sa) {
     constexpr uint32_t kMergeTile = kBlock * ITEMS;
     __shared__ Key4 s_key[kMergeTile];
     __shared__ uint32_t s_pos[kMergeTile];
@@ -1057,7 +1146,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(const Rec<CH> *__restrict__ re
         else pos = d.pos_of(min((uint32_t)B[b0 + (i - na)], d.m - 1));
         pos = min(pos, d.n - 1);
         s_pos[i] = pos;
-        s_key[i] = key_of<CH>(rec, pos);
+        s_key[i] = i < na ? merge_key<CH>(rec, symA, a0 + i, [&] { return pos; })
+                          : merge_key<CH>(rec, symB, b0 + (i - na), [&] { return pos; });
     }
     __syncthreads();
     const Key4 *sA = s_key;
@@ -1515,9 +1605,11 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     // the next suffix) and put back into its slots.
     const uint32_t ms0_cap = min(d.n0, d.n / 4u + 2u);
     uint32_t *sub0_slot = nullptr, *sub0_pos = nullptr;
+    uint32_t *symA = nullptr, *symB = nullptr;   // merge symbols (see k_msym_write); symA is Step 2's vals0
     if (parent_order || !run) {
         LOR_TAKE(ar, uint32_t, ms0_cap, sub0_slot);
         LOR_TAKE(ar, uint32_t, ms0_cap, sub0_pos);
+        LOR_TAKE(ar, uint32_t, d.m, symB);
     }
     if (parent_order) {
         const uint32_t Gn = scan_groups(d.n), G0 = scan_groups(d.n0);
@@ -1587,30 +1679,43 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
         }
         const int32_t *B = sa12 + d.dummy;
         const uint32_t nB = d.m - d.dummy;
+        if (parent_order) {
+            // A's flagged symbols came with Step 2; B's from P (this level's
+            // SA buffer, still the parent's order here)
+            symA = vals0;
+            const uint32_t Gn = scan_groups(d.n);
+            LOR_LAUNCH("k_po_count", 4.0 * d.n, s,
+                       hipLaunchKernelGGL(k_po_count, dim3(Gn), dim3(kBlock), 0, s, sa, d.n, Gn, gcount2));
+            LOR_TRY(scan_block_totals(gcount2, Gn, nullptr, s));
+            LOR_LAUNCH("k_msym_write", 8.0 * d.n + 4.0 * d.m, s,
+                       hipLaunchKernelGGL(k_msym_write, dim3(Gn), dim3(kBlock), 0, s, sa, pnames, d, Gn, gcount2,
+                                          symB));
+        }
         const uint32_t cparts = div_up(parts, kCoarse);
         LOR_LAUNCH("k_merge_partition", (double)(cparts + 1) * 4, s,
                    hipLaunchKernelGGL(k_merge_partition<CH>, dim3(div_up(cparts + 1, kBlock)), dim3(kBlock), 0, s,
                                       rec, A, d.n0, B, nB, d, cparts, (uint64_t)mtile * kCoarse, nullptr, 0u,
-                                      csplit));
+                                      symA, symB, csplit));
         LOR_LAUNCH("k_merge_partition", (double)(parts + 1) * 4, s,
                    hipLaunchKernelGGL(k_merge_partition<CH>, dim3(div_up(parts + 1, kBlock)), dim3(kBlock), 0, s,
-                                      rec, A, d.n0, B, nB, d, parts, (uint64_t)mtile, csplit, cparts, split));
+                                      rec, A, d.n0, B, nB, d, parts, (uint64_t)mtile, csplit, cparts, symA, symB,
+                                      split));
         const double mbytes = (double)n * (4 + 4 + sizeof(Rec<CH>));
         switch (mitems) {
             case 4:
                 LOR_LAUNCH("k_merge", mbytes, s,
                            hipLaunchKernelGGL((k_merge<CH, 4>), dim3(parts), dim3(kBlock), 0, s, rec, A, d.n0, B, nB,
-                                              d, split, sa));
+                                              d, split, symA, symB, sa));
                 break;
             case 12:
                 LOR_LAUNCH("k_merge", mbytes, s,
                            hipLaunchKernelGGL((k_merge<CH, 12>), dim3(parts), dim3(kBlock), 0, s, rec, A, d.n0, B, nB,
-                                              d, split, sa));
+                                              d, split, symA, symB, sa));
                 break;
             default:
                 LOR_LAUNCH("k_merge", mbytes, s,
                            hipLaunchKernelGGL((k_merge<CH, 8>), dim3(parts), dim3(kBlock), 0, s, rec, A, d.n0, B, nB,
-                                              d, split, sa));
+                                              d, split, symA, symB, sa));
                 break;
         }
     }

@@ -320,6 +320,40 @@ def test_rmq_range_and_pair_queries(n_bases, compact):
 
 # ------------------------------------------------------- larger workloads
 
+_TRACE_CHILD = """
+import sys
+sys.path.insert(0, sys.argv[1])
+import torch
+from paper_1404_3448_amd import lor, synth
+w = synth.long_text(seed=int(sys.argv[2]), num_seqs=2, seq_len=int(sys.argv[3]), num_queries=1)
+lor.lor_build_sa(torch.from_numpy(w.concat).cuda(), w.offsets)
+torch.cuda.synchronize()
+"""
+
+
+@pytest.mark.parametrize("seed", [31, 32])
+def test_deep_levels_from_parent_order(seed):
+    """Noncoding-like text with tandem repeats (2 x 2^21 bases): its deep DC3
+    levels take the parent-order path (first-symbol order from the parent
+    level, merge records only for repeating first symbols), as the level trace
+    of the same call in a child process shows; SA and LCP equal the oracle's."""
+    import os
+    import subprocess
+    seq_len = 1 << 21
+    env = dict(os.environ, LOR_TRACE="1")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    say("parent-order trace child", seed)
+    tr = subprocess.run([sys.executable, "-c", _TRACE_CHILD, root, str(seed), str(seq_len)], env=env,
+                        capture_output=True, text=True, timeout=300)
+    assert tr.returncode == 0, tr.stderr[-2000:]
+    assert tr.stderr.count("parent-order") >= 2, tr.stderr[-2000:]
+    w = synth.long_text(seed=seed, num_seqs=2, seq_len=seq_len, num_queries=1)
+    r = lor.longest_overlap_region(dev(w.concat), w.offsets)
+    joined = oracle.join(w.concat, w.offsets)
+    want_sa = oracle.suffix_array(joined)
+    assert np.array_equal(host(r["sa"]), want_sa)
+    assert np.array_equal(host(r["lcp"]), oracle.lcp(joined, want_sa))
+
 def test_noncoding_pair_8m():
     """The 8M + 8M workload at full size: SA and LCP equal the oracle's
     (comparison sort + direct LCP), and so does the overlap."""
