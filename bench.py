@@ -50,14 +50,8 @@ WORKLOADS = {
 
 
 def source_hash() -> str:
-    import glob
-    import hashlib
-    h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1404_3448_amd", "csrc", "*"))):
-        h.update(os.path.basename(p).encode())
-        with open(p, "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()
+    from paper_1404_3448_amd.build import source_hash as h
+    return h()
 
 
 def committed_traffic(kernel: str):
@@ -121,6 +115,8 @@ def bench_batched(lor, synth, torch, reps: int = 3) -> dict:
     versus a loop of the plain per-pair path, resident inputs, same results."""
     import ctypes
 
+    from paper_1404_3448_amd import autotune
+    bplan = autotune.load_batched_plan()      # tuned for the batched call (None: the process-wide plan)
     t0 = time.perf_counter()
     ws_pairs = synth.batched_pairs()
     seqs = [s for w in ws_pairs for s in w.seqs]
@@ -132,11 +128,11 @@ def bench_batched(lor, synth, torch, reps: int = 3) -> dict:
     d = torch.from_numpy(np.concatenate(seqs)).to(dev)
     out = torch.empty(P * ctypes.sizeof(lor.lor_overlap), dtype=torch.uint8, device=dev)
     ws = torch.empty(lor.lor_longest_overlap_batched_workspace(total, P), dtype=torch.uint8, device=dev)
-    lor.lor_longest_overlap_batched(d, offs, out=out, ws=ws)
+    lor.lor_longest_overlap_batched(d, offs, out=out, ws=ws, plan=bplan)
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(reps):
-        lor.lor_longest_overlap_batched(d, offs, out=out, ws=ws)
+        lor.lor_longest_overlap_batched(d, offs, out=out, ws=ws, plan=bplan)
     torch.cuda.synchronize()
     batched_s = (time.perf_counter() - t) / reps
     batched = lor.records_to_tuples(out)
@@ -144,7 +140,7 @@ def bench_batched(lor, synth, torch, reps: int = 3) -> dict:
 
     # the same call captured as a HIP graph and replayed (status() waits)
     side = torch.cuda.Stream()
-    g = lor.lor_longest_overlap_batched_graph_create(d, offs, side)
+    g = lor.lor_longest_overlap_batched_graph_create(d, offs, side, plan=bplan)
     side.synchronize()
     g.launch(side)
     g.status(side)
@@ -184,7 +180,8 @@ def bench_batched(lor, synth, torch, reps: int = 3) -> dict:
             "graph_ms": round(1e3 * graph_s, 3), "graph_pairs_per_s": round(P / graph_s, 1),
             "graph_dc3_levels": graph_levels, "graph_identical": graph_same,
             "plain_loop_ms": round(1e3 * plain_s, 3), "plain_loop_pairs_per_s": round(P / plain_s, 1),
-            "speedup": round(plain_s / batched_s, 2), "identical_to_plain": batched == plain}
+            "speedup": round(plain_s / batched_s, 2), "identical_to_plain": batched == plain,
+            "plan": bplan or "process-wide", "plan_source": "autotuned for the batched call" if bplan else "process-wide"}
 
 
 def bench_ref_queries(lor, synth, torch, reps: int = 3, loop_sample: int = 256) -> dict:
@@ -483,7 +480,8 @@ def bench_serving(seed: int = 5) -> dict:
     backlog = serve.make_requests(seed=seed + 100, count=96, qps=1e9)
     for r in backlog:
         r.arrival = 0.0
-    runner = serve.GpuRunner()
+    from paper_1404_3448_amd import autotune
+    runner = serve.GpuRunner(plan=autotune.load_batched_plan())
     warm = serve.make_requests(seed=seed + 200, count=16, qps=1e9)
     for r in warm:
         r.arrival = 0.0

@@ -9,7 +9,12 @@ JSON keyed by the GPU architecture:
   merge_items                  : suffix array of a 64M-base noncoding-like text
   plcp_steps                   : LCP of the same text
 
-A plan changes speed only; results are identical under every plan.
+then tunes a second plan for the batched entry point the same way (every
+knob, starting from the plan above) on 512 pairs of the batched workload's
+generator (pair totals log-uniform in [1e3, 1e6]), and times both plans
+against the defaults on a 256M-base text (suffix array + LCP) and on the
+batched pairs. A plan changes speed only; results are identical under every
+plan.
 
     python -m paper_1404_3448_amd.autotune [--out DIR]   # writes plans/<arch>.json (or DIR/<arch>.json)
 """
@@ -47,6 +52,15 @@ def load_tuned_plan(apply: bool = True):
     if apply:
         lor.lor_plan_set(doc["plan"])
     return doc["plan"]
+
+
+def load_batched_plan():
+    """The plan tuned for the batched entry point on this GPU (None: use the process-wide plan)."""
+    try:
+        with open(plan_path()) as f:
+            return json.load(f).get("batched_plan")
+    except OSError:
+        return None
 
 
 def _time(fn, reps: int = 3) -> float:
@@ -133,7 +147,56 @@ def tune(log=print) -> dict:
         log(f"LCP 64M: plcp_steps={steps}: {1e3 * t:.2f} ms")
     best["plcp_steps"] = int(min((k for k in meas if k.startswith("build_lcp")), key=meas.get).split("=")[1])
     lor.lor_plan_set(best)
-    return {"arch": arch_key(), "device": torch.cuda.get_device_name(0), "plan": best,
+    del seqs, joined, sa, lcp, ws_sa, ws_lcp
+
+    # the batched entry point: every knob again, on the batched workload's pairs
+    pairs = synth.batched_pairs(seed=40, num_pairs=512)
+    bseqs = [x for p in pairs for x in p.seqs]
+    boffs = np.concatenate([[0], np.cumsum([x.size for x in bseqs])]).astype(np.int64)
+    bd = torch.from_numpy(np.concatenate(bseqs)).to(dev)
+    bws = torch.empty(lor.lor_longest_overlap_batched_workspace(int(boffs[-1]), len(pairs)), dtype=torch.uint8,
+                      device=dev)
+    bout = torch.empty(len(pairs) * 32, dtype=torch.uint8, device=dev)
+    log(f"batched tuning workload: {len(pairs)} pairs, {int(boffs[-1])} bases")
+
+    def batched(plan):
+        return _time(lambda: lor.lor_longest_overlap_batched(bd, boffs, out=bout, ws=bws, plan=plan))
+
+    bbest = dict(best)
+    knobs = [("digit_bits", (6, 7, 8)), ("radix_items_u32", (8, 12, 16, 24)), ("radix_items_u64", (8, 12, 16)),
+             ("merge_items", (4, 8, 12)), ("plcp_steps", (32, 64, 128))]
+    for knob, values in knobs:
+        ts = {}
+        for v in values:
+            ts[v] = batched(dict(bbest, **{knob: v}))
+            meas[f"batched {knob}={v}"] = ts[v]
+            log(f"batched 512 pairs: {knob}={v}: {1e3 * ts[v]:.2f} ms")
+        bbest[knob] = min(ts, key=ts.get)
+    default = lor.lor_plan_default().as_dict()
+    meas["check batched default plan"] = batched(default)
+    meas["check batched batched plan"] = batched(bbest)
+    del bd, bws, bout
+
+    # both plans against the defaults on a larger text
+    w = synth.long_text(seed=5, num_seqs=4, seq_len=1 << 26, num_queries=1)
+    seqs = torch.from_numpy(w.concat).to(dev)
+    N = w.joined_length
+    joined = torch.empty(N, dtype=torch.uint8, device=dev)
+    sa = torch.empty(N, dtype=torch.int32, device=dev)
+    lcp = torch.empty(N, dtype=torch.int32, device=dev)
+    ws_sa = torch.empty(lor.lor_build_sa_workspace(int(w.offsets[-1]), 4), dtype=torch.uint8, device=dev)
+    ws_lcp = torch.empty(lor.lor_build_lcp_workspace(N), dtype=torch.uint8, device=dev)
+
+    def sa_lcp():
+        lor.lor_build_sa(seqs, w.offsets, joined_out=joined, sa_out=sa, ws=ws_sa)
+        lor.lor_build_lcp(joined, sa, lcp_out=lcp, ws=ws_lcp)
+
+    for name, plan in (("default", default), ("tuned", best)):
+        lor.lor_plan_set(plan)
+        meas[f"check sa+lcp 256M {name} plan"] = _time(sa_lcp, reps=2)
+        log(f"SA + LCP 256M, {name} plan: {1e3 * meas[f'check sa+lcp 256M {name} plan']:.1f} ms")
+    lor.lor_plan_set(best)
+    return {"arch": arch_key(), "device": torch.cuda.get_device_name(0), "plan": best, "batched_plan": bbest,
             "measurements_ms": {k: round(1e3 * v, 3) for k, v in meas.items()},
             "command": "python -m paper_1404_3448_amd.autotune"}
 

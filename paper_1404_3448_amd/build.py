@@ -37,6 +37,18 @@ def _compile(src: str) -> str:
     return obj
 
 
+def source_hash() -> str:
+    """sha256 over the kernel sources (file names and contents): the key under
+    which measured counter figures are valid."""
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(CSRC, "*"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))

@@ -99,10 +99,11 @@ class GpuRunner:
     HIP stream of default priority and a pinned staging buffer) from a pool
     that outlives the calls, so streams and pinned memory are made once."""
 
-    def __init__(self, device: str = "cuda:0"):
+    def __init__(self, device: str = "cuda:0", plan=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
+        self.plan = plan              # plan of the batched calls (None: the process-wide plan)
         self._pool = queue.SimpleQueue()
         lor.lib()
 
@@ -179,9 +180,9 @@ class GpuRunner:
             with torch.cuda.stream(s):
                 d = self._to_device(ctx, seqs, int(offs[-1]))
                 if keep:
-                    out, lcp, isa = lor.lor_longest_overlap_batched_state(d, offs, stream=s)
+                    out, lcp, isa = lor.lor_longest_overlap_batched_state(d, offs, stream=s, plan=self.plan)
                 else:
-                    out = lor.lor_longest_overlap_batched(d, offs, stream=s)
+                    out = lor.lor_longest_overlap_batched(d, offs, stream=s, plan=self.plan)
                 recs = lor.records_to_tuples(out)   # the call synchronised the stream
                 states = [None] * len(reqs)
                 if keep:
@@ -413,3 +414,38 @@ def make_requests(seed: int = 5, count: int = 400, qps: float = 100.0, lo: float
             delay = float(rng.exponential(followup_mean))
         out.append(Request(i, a, b, t, keep, fol, delay))
     return out
+
+
+def main():
+    """The serving scenario on cuda:0: capacity on a backlog, then Poisson
+    arrivals at a fraction of it; prints one JSON line of stats."""
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="continuous-batching serving run on one GPU")
+    ap.add_argument("--backlog", type=int, default=96, help="requests of the capacity run (all at t = 0)")
+    ap.add_argument("--count", type=int, default=400, help="requests of the Poisson run")
+    ap.add_argument("--load", type=float, default=0.7, help="offered rate as a fraction of the capacity")
+    ap.add_argument("--seed", type=int, default=5)
+    args = ap.parse_args()
+    from . import autotune
+    lor.lib()
+    autotune.load_tuned_plan()
+    runner = GpuRunner(plan=autotune.load_batched_plan())
+    warm = make_requests(seed=args.seed + 200, count=16, qps=1e9)
+    for r in warm:
+        r.arrival = 0.0
+    Server(runner=runner, batch_max=4).run(warm)
+    backlog = make_requests(seed=args.seed + 100, count=args.backlog, qps=1e9)
+    for r in backlog:
+        r.arrival = 0.0
+    cap = Server(runner=runner).run(backlog)
+    print(f"capacity: {cap['result_pairs_per_s']} pairs/s", file=sys.stderr, flush=True)
+    reqs = make_requests(seed=args.seed, count=args.count, qps=args.load * cap["result_pairs_per_s"])
+    stats = Server(runner=runner).run(reqs)
+    stats["capacity_pairs_per_s"] = cap["result_pairs_per_s"]
+    print(json.dumps(stats))
+
+
+if __name__ == "__main__":
+    main()
