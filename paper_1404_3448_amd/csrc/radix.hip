@@ -153,13 +153,15 @@ __global__ __launch_bounds__(kBlock, 2) void k_radix_scatter(const K *__restrict
     __shared__ uint32_t s_delta[kBins];      // global index minus tile slot, per digit
     __shared__ uint32_t s_tmp[W];
     // The per-wave lane masks of one item's digit are dead once the ranks are
-    // known, before the tile is reordered: they share LDS with the tile.
+    // known, before the tile is reordered: they share LDS with the tile, which
+    // is reordered in two rounds (keys, then values) through the same bytes,
+    // so a workgroup of 64-bit keys takes 38 KB of LDS instead of 54 KB.
     constexpr size_t kMatchBytes = sizeof(uint64_t) * W * kBins;
-    constexpr size_t kTileBytes = (sizeof(K) + sizeof(uint32_t)) * TILE;
+    constexpr size_t kTileBytes = sizeof(K) * TILE;
     __shared__ __align__(16) unsigned char s_raw[kMatchBytes > kTileBytes ? kMatchBytes : kTileBytes];
     uint64_t(*s_match)[kBins] = reinterpret_cast<uint64_t(*)[kBins]>(s_raw);
     K *s_key = reinterpret_cast<K *>(s_raw);
-    uint32_t *s_val = reinterpret_cast<uint32_t *>(s_raw + sizeof(K) * TILE);
+    uint32_t *s_val = reinterpret_cast<uint32_t *>(s_raw);
 
     uint32_t t;
     if (!xcd_tile(tiles, &t)) return;
@@ -252,31 +254,40 @@ __global__ __launch_bounds__(kBlock, 2) void k_radix_scatter(const K *__restrict
     s_delta[tid] = gbase - start;
     __syncthreads();
 
+    uint32_t lp[ITEMS];   // tile slot of each item, TILE when it has none
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const uint32_t d = dr[r] & 511u;
-        const uint32_t lp = s_cnt[w][min(d, (uint32_t)kBins - 1u)] + (dr[r] >> 9);
-        if (d < kBins && lp < TILE) {   // always true for a consistent ranking
-            s_key[lp] = k[r];
-            s_val[lp] = v[r];
-        }
+        const uint32_t x = s_cnt[w][min(d, (uint32_t)kBins - 1u)] + (dr[r] >> 9);
+        lp[r] = (d < kBins && x < TILE) ? x : TILE;   // always a slot for a consistent ranking
+        if (lp[r] < TILE) s_key[lp[r]] = k[r];
     }
     __syncthreads();
 
     // Slot i holds the element that goes to s_delta[digit] + i.
+    uint32_t go[ITEMS];
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const uint32_t i = r * kBlock + tid;
+        go[r] = 0xffffffffu;
         if (i < nvalid) {
             const K key = s_key[i];
             const uint32_t d = (uint32_t)(key >> shift) & mask;
             const uint32_t g = s_delta[d] + i;
             if (g < n) {                    // always true for a consistent count table
                 kout[g] = key;
-                vout[g] = s_val[i];
+                go[r] = g;
             }
         }
     }
+    __syncthreads();   // every key has left the tile: the values take its place
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r)
+        if (lp[r] < TILE) s_val[lp[r]] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r)
+        if (go[r] != 0xffffffffu) vout[go[r]] = s_val[r * kBlock + tid];
 }
 
 // Exclusive scan of `count` words in place by one 1024-thread workgroup;
