@@ -529,13 +529,16 @@ template <> struct Rec<uint8_t> { uint4 a; };
 template <> struct Rec<int32_t> { uint4 a, b; };
 template <> struct Rec<uint16_t> { uint4 a, b; };
 
+// RT picks the layout: Rec<uint8_t> (one uint4) for any text whose symbols
+// fit a byte (byte texts, and int32 texts of at most 255 symbols such as the
+// level over the byte text's triple names), the two-uint4 form otherwise.
 // For q < n0 it also writes Step 2's pair of the mod-0 suffix 3q: slot[q] =
 // rank of suffix 3q+1 minus one (read from rank12 itself: when n mod 3 = 1
 // the last one is the padding-only position n) and sym0[q] = t_{3q}.
-template <typename CH>
+template <typename CH, typename RT>
 __global__ __launch_bounds__(kBlock) void k_records(const CH *__restrict__ t, Dims d,
                                                     const int32_t *__restrict__ rank12,
-                                                    Rec<CH> *__restrict__ rec, uint32_t *__restrict__ slot,
+                                                    Rec<RT> *__restrict__ rec, uint32_t *__restrict__ slot,
                                                     uint32_t *__restrict__ sym0) {
     const uint32_t nq = d.n0 + 1;
     for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < nq; q += gridDim.x * kBlock) {
@@ -544,8 +547,8 @@ __global__ __launch_bounds__(kBlock) void k_records(const CH *__restrict__ t, Di
                        c3 = sym(t, d.n, p + 3);
         const uint32_t r1 = rank_at(rank12, d, p + 1), r2 = rank_at(rank12, d, p + 2),
                        r4 = rank_at(rank12, d, p + 4);
-        Rec<CH> x;
-        if constexpr (sizeof(CH) == 1) {
+        Rec<RT> x;
+        if constexpr (sizeof(RT) == 1) {
             x.a = make_uint4(c0 | (c1 << 8) | (c2 << 16) | (c3 << 24), r1, r2, r4);
         } else {
             x.a = make_uint4(c0, c1, c2, c3);
@@ -1063,8 +1066,8 @@ __global__ __launch_bounds__(kBlock) void k_msym_write(const int32_t *__restrict
 // `diag` outputs, by binary search inside [lo, hi] (which must hold it).
 // Key of merge input element j (symbols as above; sym == nullptr: always
 // from the record). pos() gives the element's text position.
-template <typename CH, typename POS>
-__device__ __forceinline__ Key4 merge_key(const Rec<CH> *rec, const uint32_t *sym, uint32_t j, POS pos) {
+template <typename RT, typename POS>
+__device__ __forceinline__ Key4 merge_key(const Rec<RT> *rec, const uint32_t *sym, uint32_t j, POS pos) {
     if (sym) {
         const uint32_t x = sym[j];
         if (!(x >> 31)) {
@@ -1074,17 +1077,17 @@ __device__ __forceinline__ Key4 merge_key(const Rec<CH> *rec, const uint32_t *sy
             return k;
         }
     }
-    return key_of<CH>(rec, pos());
+    return key_of<RT>(rec, pos());
 }
 
-template <typename CH>
-__device__ __forceinline__ uint32_t merge_split(const Rec<CH> *rec, const uint32_t *A, const int32_t *B,
+template <typename RT>
+__device__ __forceinline__ uint32_t merge_split(const Rec<RT> *rec, const uint32_t *A, const int32_t *B,
                                                 const uint32_t *symA, const uint32_t *symB, const Dims &d,
                                                 uint32_t diag, uint32_t lo, uint32_t hi) {
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1, bj = diag - 1 - mid;
-        const Key4 a = merge_key<CH>(rec, symA, mid, [&] { return min(A[mid], d.n - 1); });
-        const Key4 b = merge_key<CH>(rec, symB, bj,
+        const Key4 a = merge_key<RT>(rec, symA, mid, [&] { return min(A[mid], d.n - 1); });
+        const Key4 b = merge_key<RT>(rec, symB, bj,
                                      [&] { return min(d.pos_of(min((uint32_t)B[bj], d.m - 1)), d.n - 1); });
         if (!sample_less(b, a)) lo = mid + 1; else hi = mid;
     }
@@ -1098,8 +1101,8 @@ __device__ __forceinline__ uint32_t merge_split(const Rec<CH> *rec, const uint32
 // of every later search.
 constexpr uint32_t kCoarse = 64;
 
-template <typename CH>
-__global__ __launch_bounds__(kBlock) void k_merge_partition(const Rec<CH> *__restrict__ rec,
+template <typename RT>
+__global__ __launch_bounds__(kBlock) void k_merge_partition(const Rec<RT> *__restrict__ rec,
                                                             const uint32_t *__restrict__ A, uint32_t nA,
                                                             const int32_t *__restrict__ B, uint32_t nB,
                                                             Dims d, uint32_t parts, uint64_t tile,
@@ -1117,11 +1120,11 @@ __global__ __launch_bounds__(kBlock) void k_merge_partition(const Rec<CH> *__res
         lo = min(max(lo0, coarse[c]), hi0);
         hi = max(min(hi0, coarse[min(c + 1, cparts)]), lo);
     }
-    split[p] = merge_split<CH>(rec, A, B, symA, symB, d, diag, lo, hi);
+    split[p] = merge_split<RT>(rec, A, B, symA, symB, d, diag, lo, hi);
 }
 
-template <typename CH, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_merge(const Rec<CH> *__restrict__ rec,
+template <typename RT, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_merge(const Rec<RT> *__restrict__ rec,
                                                   const uint32_t *__restrict__ A, uint32_t nA,
                                                   const int32_t *__restrict__ B, uint32_t nB, Dims d,
                                                   const uint32_t *__restrict__ split,
@@ -1146,8 +1149,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(const Rec<CH> *__restrict__ re
         else pos = d.pos_of(min((uint32_t)B[b0 + (i - na)], d.m - 1));
         pos = min(pos, d.n - 1);
         s_pos[i] = pos;
-        s_key[i] = i < na ? merge_key<CH>(rec, symA, a0 + i, [&] { return pos; })
-                          : merge_key<CH>(rec, symB, b0 + (i - na), [&] { return pos; });
+        s_key[i] = i < na ? merge_key<RT>(rec, symA, a0 + i, [&] { return pos; })
+                          : merge_key<RT>(rec, symB, b0 + (i - na), [&] { return pos; });
     }
     __syncthreads();
     const Key4 *sA = s_key;
@@ -1210,6 +1213,51 @@ lor_status decided_count(uint32_t *hdr, int word, uint32_t *out, hipStream_t s) 
 }
 
 enum KeyMode { KM_U32, KM_U64, KM_STAGED };
+
+// Step 3 launches: coarse then fine merge-path splits, then the merge.
+struct MergeArgs {
+    const uint32_t *A;
+    uint32_t nA;
+    const int32_t *B;
+    uint32_t nB;
+    Dims d;
+    uint32_t parts, cparts, mtile;
+    int mitems;
+    uint32_t *csplit, *split;
+    const uint32_t *symA, *symB;
+    int32_t *sa;
+};
+
+template <typename RT>
+lor_status launch_merge(const Rec<RT> *rec, const MergeArgs &m, hipStream_t s) {
+    LOR_LAUNCH("k_merge_partition", (double)(m.cparts + 1) * 4, s,
+               hipLaunchKernelGGL(k_merge_partition<RT>, dim3(div_up(m.cparts + 1, kBlock)), dim3(kBlock), 0, s, rec,
+                                  m.A, m.nA, m.B, m.nB, m.d, m.cparts, (uint64_t)m.mtile * kCoarse, nullptr, 0u, m.symA,
+                                  m.symB, m.csplit));
+    LOR_LAUNCH("k_merge_partition", (double)(m.parts + 1) * 4, s,
+               hipLaunchKernelGGL(k_merge_partition<RT>, dim3(div_up(m.parts + 1, kBlock)), dim3(kBlock), 0, s, rec,
+                                  m.A, m.nA, m.B, m.nB, m.d, m.parts, (uint64_t)m.mtile, m.csplit, m.cparts, m.symA,
+                                  m.symB, m.split));
+    const double mbytes = (double)m.d.n * (4 + 4 + sizeof(Rec<RT>));
+    switch (m.mitems) {
+        case 4:
+            LOR_LAUNCH("k_merge", mbytes, s,
+                       hipLaunchKernelGGL((k_merge<RT, 4>), dim3(m.parts), dim3(kBlock), 0, s, rec, m.A, m.nA, m.B,
+                                          m.nB, m.d, m.split, m.symA, m.symB, m.sa));
+            break;
+        case 12:
+            LOR_LAUNCH("k_merge", mbytes, s,
+                       hipLaunchKernelGGL((k_merge<RT, 12>), dim3(m.parts), dim3(kBlock), 0, s, rec, m.A, m.nA, m.B,
+                                          m.nB, m.d, m.split, m.symA, m.symB, m.sa));
+            break;
+        default:
+            LOR_LAUNCH("k_merge", mbytes, s,
+                       hipLaunchKernelGGL((k_merge<RT, 8>), dim3(m.parts), dim3(kBlock), 0, s, rec, m.A, m.nA, m.B,
+                                          m.nB, m.d, m.split, m.symA, m.symB, m.sa));
+            break;
+    }
+    return LOR_OK;
+}
 
 template <typename CH>
 lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Arena &ar, uint32_t *hdr,
@@ -1580,12 +1628,22 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
     uint32_t *keys0, *vals0, *keys1, *vals1, *sc0, *sc1, *counts2;
     LOR_TAKE(ar, uint32_t, d.n0, keys0);
     LOR_TAKE(ar, uint32_t, d.n0, vals0);
-    if (run)
-        LOR_LAUNCH("k_records",
-                   (double)(d.n0 + 1) * (sizeof(Rec<CH>) + 12) + (double)n * sizeof(CH) + (parent_order ? 0.0 : 8.0 * d.n0),
-                   s,
-                   hipLaunchKernelGGL(k_records<CH>, dim3(grid_for(d.n0 + 1)), dim3(kBlock), 0, s, t, d, rank12,
-                                      rec, parent_order ? nullptr : keys0, parent_order ? nullptr : vals0));
+    // records in one uint4 when every symbol fits a byte (sized above for the wide form)
+    const bool narrow_rec = sizeof(CH) == 1 || (sizeof(CH) == 4 && alphabet <= 255u);
+    Rec<uint8_t> *rec8 = reinterpret_cast<Rec<uint8_t> *>(rec);
+    if (run) {
+        const double rbytes = (double)(d.n0 + 1) * ((narrow_rec ? sizeof(Rec<uint8_t>) : sizeof(Rec<CH>)) + 12) +
+                              (double)n * sizeof(CH) + (parent_order ? 0.0 : 8.0 * d.n0);
+        if (narrow_rec)
+            LOR_LAUNCH("k_records", rbytes, s,
+                       hipLaunchKernelGGL((k_records<CH, uint8_t>), dim3(grid_for(d.n0 + 1)), dim3(kBlock), 0, s, t,
+                                          d, rank12, rec8, parent_order ? nullptr : keys0,
+                                          parent_order ? nullptr : vals0));
+        else
+            LOR_LAUNCH("k_records", rbytes, s,
+                       hipLaunchKernelGGL((k_records<CH, CH>), dim3(grid_for(d.n0 + 1)), dim3(kBlock), 0, s, t, d,
+                                          rank12, rec, parent_order ? nullptr : keys0, parent_order ? nullptr : vals0));
+    }
 
     // ---- Step 2: mod-0 suffixes
     LOR_TAKE(ar, uint32_t, d.n0, keys1);
@@ -1691,33 +1749,10 @@ lor_status dc3_level(const CH *t, uint32_t n, uint32_t alphabet, int32_t *sa, Ar
                        hipLaunchKernelGGL(k_msym_write, dim3(Gn), dim3(kBlock), 0, s, sa, pnames, d, Gn, gcount2,
                                           symB));
         }
-        const uint32_t cparts = div_up(parts, kCoarse);
-        LOR_LAUNCH("k_merge_partition", (double)(cparts + 1) * 4, s,
-                   hipLaunchKernelGGL(k_merge_partition<CH>, dim3(div_up(cparts + 1, kBlock)), dim3(kBlock), 0, s,
-                                      rec, A, d.n0, B, nB, d, cparts, (uint64_t)mtile * kCoarse, nullptr, 0u,
-                                      symA, symB, csplit));
-        LOR_LAUNCH("k_merge_partition", (double)(parts + 1) * 4, s,
-                   hipLaunchKernelGGL(k_merge_partition<CH>, dim3(div_up(parts + 1, kBlock)), dim3(kBlock), 0, s,
-                                      rec, A, d.n0, B, nB, d, parts, (uint64_t)mtile, csplit, cparts, symA, symB,
-                                      split));
-        const double mbytes = (double)n * (4 + 4 + sizeof(Rec<CH>));
-        switch (mitems) {
-            case 4:
-                LOR_LAUNCH("k_merge", mbytes, s,
-                           hipLaunchKernelGGL((k_merge<CH, 4>), dim3(parts), dim3(kBlock), 0, s, rec, A, d.n0, B, nB,
-                                              d, split, symA, symB, sa));
-                break;
-            case 12:
-                LOR_LAUNCH("k_merge", mbytes, s,
-                           hipLaunchKernelGGL((k_merge<CH, 12>), dim3(parts), dim3(kBlock), 0, s, rec, A, d.n0, B, nB,
-                                              d, split, symA, symB, sa));
-                break;
-            default:
-                LOR_LAUNCH("k_merge", mbytes, s,
-                           hipLaunchKernelGGL((k_merge<CH, 8>), dim3(parts), dim3(kBlock), 0, s, rec, A, d.n0, B, nB,
-                                              d, split, symA, symB, sa));
-                break;
-        }
+        const MergeArgs ma{A, d.n0, B, nB, d, parts, div_up(parts, kCoarse), mtile, mitems, csplit, split, symA,
+                           symB, sa};
+        if (narrow_rec) LOR_TRY(launch_merge<uint8_t>(rec8, ma, s));
+        else LOR_TRY(launch_merge<CH>(rec, ma, s));
     }
     ar.release(mark_level);
     return LOR_OK;
