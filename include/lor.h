@@ -43,7 +43,8 @@ enum {
     LOR_ETOOLARGE = 3,   /* joined length would exceed 2^31 - 1 */
     LOR_EWORKSPACE = 4,  /* workspace smaller than the size query returned */
     LOR_EHIP = 5,        /* a HIP runtime call failed (see lor_last_error) */
-    LOR_ESTALE = 6       /* an RMQ handle does not match the arrays passed */
+    LOR_ESTALE = 6       /* an RMQ handle does not match the arrays passed, or a replayed
+                            graph's data no longer fit its launch sequence */
 };
 
 /* Static description of a status code. */
@@ -350,6 +351,18 @@ typedef struct {
 void lor_plan_default(lor_plan *out);
 void lor_plan_get(lor_plan *out);
 lor_status lor_plan_set(const lor_plan *plan);
+
+/* ------------------------------------------------------- deferred errors
+ * A condition found on the device (a base outside 0..3; under a replayed
+ * HIP graph, data that no longer fit the captured launch sequence) is
+ * written into the first words of the call's workspace. The next
+ * synchronous step of the call returns it; lor_check returns it for the
+ * workspace of any lor_build_sa, lor_suffix_array_i32,
+ * lor_longest_overlap_batched(_state) or lor_longest_overlap_ref call once
+ * the stream has run it: synchronises hip_stream, then LOR_OK,
+ * LOR_EALPHABET or LOR_ESTALE (a graph's data changed). Other workspaces
+ * have no such header. */
+lor_status lor_check(const void *ws, void *hip_stream);
 
 /* --------------------------------------------------------- kernel timing
  * Optional per-kernel timing with HIP events recorded on the launch stream

@@ -269,7 +269,7 @@ const char *lor_status_string(lor_status s) {
         case LOR_ETOOLARGE: return "joined text longer than 2^31-1";
         case LOR_EWORKSPACE: return "workspace too small";
         case LOR_EHIP: return "HIP runtime error";
-        case LOR_ESTALE: return "RMQ handle does not match the arrays";
+        case LOR_ESTALE: return "stale state: an RMQ handle or a replayed graph no longer fits the data";
         default: return "unknown status";
     }
 }
@@ -692,13 +692,13 @@ lor_status lor_longest_overlap_batched_graph_launch(lor_batched_graph *graph, vo
     return LOR_OK;
 }
 
-lor_status lor_longest_overlap_batched_graph_status(lor_batched_graph *graph, void *hip_stream) {
-    if (!graph) {
-        set_error("NULL graph");
+lor_status lor_check(const void *ws, void *hip_stream) {
+    if (!ws || !aligned(ws, 256)) {
+        set_error("workspace pointer is NULL or not 256-byte aligned");
         return LOR_EINVAL;
     }
     uint32_t words[16];
-    LOR_HIP(hipMemcpyAsync(words, graph->hdr, sizeof(words), hipMemcpyDeviceToHost, (hipStream_t)hip_stream));
+    LOR_HIP(hipMemcpyAsync(words, ws, sizeof(words), hipMemcpyDeviceToHost, (hipStream_t)hip_stream));
     LOR_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
     if (words[0]) {
         set_error("input base outside 0..3");
@@ -709,6 +709,14 @@ lor_status lor_longest_overlap_batched_graph_status(lor_batched_graph *graph, vo
         return LOR_ESTALE;
     }
     return LOR_OK;
+}
+
+lor_status lor_longest_overlap_batched_graph_status(lor_batched_graph *graph, void *hip_stream) {
+    if (!graph) {
+        set_error("NULL graph");
+        return LOR_EINVAL;
+    }
+    return lor_check(graph->hdr, hip_stream);
 }
 
 int32_t lor_longest_overlap_batched_graph_levels(const lor_batched_graph *graph) {

@@ -118,6 +118,7 @@ def lib():
         "lor_plan_default": ([ctypes.POINTER(lor_plan)], None),
         "lor_plan_get": ([ctypes.POINTER(lor_plan)], None),
         "lor_plan_set": ([ctypes.POINTER(lor_plan)], I32),
+        "lor_check": ([P, P], I32),
         "lor_timing_enable": ([I32], None),
         "lor_timing_only": ([ctypes.c_char_p], None),
         "lor_timing_reset": ([], None),
@@ -647,6 +648,11 @@ def make_plan(**fields) -> lor_plan:
 
 
 # ----------------------------------------------------------------- timing
+
+def lor_check(ws, stream=None) -> int:
+    """Status the device left in a call's workspace header (synchronises the stream)."""
+    return int(lib().lor_check(_ptr(ws), _stream(stream)))
+
 
 def lor_timing_enable(on: bool = True):
     lib().lor_timing_enable(1 if on else 0)

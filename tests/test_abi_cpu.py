@@ -213,3 +213,9 @@ def test_batched_state_argument_errors(L):
         lor.LOR_EWORKSPACE
     assert L.lor_longest_overlap_batched_state(FAKE, op, 0, None, FAKE, FAKE, FAKE, FAKE, ws, None) == lor.LOR_EINVAL
     assert list(lor.pair_starts([0, 5, 9, 9, 12])) == [0, 11, 16]
+
+
+def test_lor_check_argument_errors(L):
+    assert L.lor_check(None, None) == lor.LOR_EINVAL
+    assert L.lor_check(ctypes.c_void_p((1 << 20) + 8), None) == lor.LOR_EINVAL
+    assert L.lor_status_string(lor.LOR_ESTALE).startswith(b"stale")

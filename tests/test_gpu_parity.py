@@ -227,6 +227,21 @@ def test_build_sa_rejects_bad_base():
     assert e.value.status == lor.LOR_EALPHABET
 
 
+def test_lor_check_reads_the_workspace_header():
+    """lor_check returns what the device left in a call's workspace header:
+    nothing after a good call, the bad base after a bad one."""
+    good, goff = build([[0, 1, 2, 3], [3, 2, 1]])
+    bad, boff = build([[0, 1, 2], [3, 7, 1]])
+    ws = torch.empty(lor.lor_build_sa_workspace(8, 2), dtype=torch.uint8, device="cuda")
+    lor.lor_build_sa(good, goff, ws=ws)
+    assert lor.lor_check(ws) == lor.LOR_OK
+    with pytest.raises(lor.LorError):
+        lor.lor_build_sa(bad, boff, ws=ws)
+    assert lor.lor_check(ws) == lor.LOR_EALPHABET
+    lor.lor_build_sa(good, goff, ws=ws)   # every call clears the header first
+    assert lor.lor_check(ws) == lor.LOR_OK
+
+
 def test_repeated_calls_are_bit_identical():
     w = synth.noncoding_pair(seed=21, n=300_000, segments=4)
     d, offs = dev(w.concat), w.offsets
