@@ -418,7 +418,10 @@ def make_requests(seed: int = 5, count: int = 400, qps: float = 100.0, lo: float
 
 def main():
     """The serving scenario on cuda:0: capacity on a backlog, then Poisson
-    arrivals at a fraction of it; prints one JSON line of stats."""
+    arrivals at a fraction of it; prints one JSON line of stats. Every request
+    is generated before the first GPU call, and the phases (warm-up, capacity,
+    Poisson run) are half a second apart, so a kernel trace of the run splits
+    into them at its idle gaps."""
     import argparse
     import json
     import sys
@@ -429,21 +432,27 @@ def main():
     ap.add_argument("--seed", type=int, default=5)
     args = ap.parse_args()
     from . import autotune
+    warm = make_requests(seed=args.seed + 200, count=16, qps=1e9)
+    backlog = make_requests(seed=args.seed + 100, count=args.backlog, qps=1e9)
+    for r in warm + backlog:
+        r.arrival = 0.0
+    reqs = make_requests(seed=args.seed, count=args.count, qps=1.0)   # arrival times rescaled below
     lor.lib()
     autotune.load_tuned_plan()
     runner = GpuRunner(plan=autotune.load_batched_plan())
-    warm = make_requests(seed=args.seed + 200, count=16, qps=1e9)
-    for r in warm:
-        r.arrival = 0.0
     Server(runner=runner, batch_max=4).run(warm)
-    backlog = make_requests(seed=args.seed + 100, count=args.backlog, qps=1e9)
-    for r in backlog:
-        r.arrival = 0.0
+    time.sleep(0.5)
     cap = Server(runner=runner).run(backlog)
-    print(f"capacity: {cap['result_pairs_per_s']} pairs/s", file=sys.stderr, flush=True)
-    reqs = make_requests(seed=args.seed, count=args.count, qps=args.load * cap["result_pairs_per_s"])
+    qps = args.load * cap["result_pairs_per_s"]
+    print(f"capacity: {cap['result_pairs_per_s']} pairs/s; offering {qps:.1f} requests/s", file=sys.stderr,
+          flush=True)
+    for r in reqs:   # exponential gaps scale with 1 / qps
+        r.arrival /= qps
+    time.sleep(0.5)
     stats = Server(runner=runner).run(reqs)
     stats["capacity_pairs_per_s"] = cap["result_pairs_per_s"]
+    stats["capacity_p50_ms"] = cap["p50_ms"]
+    stats["offered_qps"] = round(qps, 1)
     print(json.dumps(stats))
 
 
