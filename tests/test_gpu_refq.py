@@ -89,15 +89,16 @@ def test_ref_noncoding_many_queries():
         queries.append(q)
     got = run(ref, queries)
     check(ref, queries[:12], got[:12])          # the DP oracle on a sample of the queries
-    # the rest against the plain path on each (query, reference) pair
-    for q in range(12, len(queries), 5):
-        query = queries[q]
-        offs = np.array([0, query.size, query.size + ref.size], np.int64)
-        d = torch.from_numpy(np.concatenate([query, ref])).cuda()
-        plain = lor.longest_overlap_region(d, offs)["overlap"]
-        assert got[q][0] == plain[0], q
-        if plain[0]:
-            assert got[q][2] == plain[2], q
+    # every query against the oracle's scan of its (query, reference) pair, in CPU
+    # worker processes: the length and the smallest query offset are unique, the
+    # reference offset must hold the same substring
+    import oracle_pool
+    want = oracle_pool.pairs_overlap([(q, ref) for q in queries])
+    for q, (query, (L, _, op, _, _)) in enumerate(zip(queries, want)):
+        assert got[q][0] == L, q
+        if L:
+            assert got[q][2] == op, q
+            assert np.array_equal(query[op:op + L], ref[got[q][4]:got[q][4] + L]), q
 
 
 def test_ref_rejects_bad_base():
