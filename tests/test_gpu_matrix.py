@@ -144,10 +144,11 @@ def first_shared_window(a, b, L):
 def test_matrix_across_chunks_and_unaligned():
     """Three noncoding-like sequences of 3M bases with shared mutated
     segments: 9M ranks span several chunks of the two-level tile scan.
-    Every pair's length equals the single-pair path, off_p is the first
-    offset in a whose length-L window occurs in b, off_q holds the same
-    substring; an sa/lcp pair 4 bytes off 16-byte alignment (the scalar
-    load path) gives identical records."""
+    Every record (a, b) equals the oracle's overlap of a and b alone in
+    length and off_p (the first offset in a whose length-L window occurs in
+    b, also found by direct search), off_q holds the same substring; an
+    sa/lcp pair 4 bytes off 16-byte alignment (the scalar load path) gives
+    identical records."""
     rng = synth.rng_for(92)
     k = 3
     seqs = [synth.noncoding_like(rng, 3_000_000) for _ in range(k)]
@@ -171,15 +172,16 @@ def test_matrix_across_chunks_and_unaligned():
     assert sa_buf[1:].data_ptr() % 16 == 4
     unaligned = lor.records_to_tuples(lor.lor_overlap_matrix(sa_buf[1:], lcp_buf[1:], offs))
     assert unaligned == recs
+    import oracle_pool
+    ab = [(a, b) for a in range(k) for b in range(k) if a != b]
+    want = dict(zip(ab, oracle_pool.pairs_overlap([(seqs[a], seqs[b]) for a, b in ab], procs=len(ab))))
     for a in range(k):
         assert recs[a * k + a] == (0, -1, -1, -1, -1)
         for b in range(k):
             if a == b:
                 continue
             L, sp, op, sq, oq = recs[a * k + b]
-            po = np.array([0, seqs[a].size, seqs[a].size + seqs[b].size], np.int64)
-            pd = torch.from_numpy(np.concatenate([seqs[a], seqs[b]])).cuda()
-            assert L == lor.longest_overlap_region(pd, po)["overlap"][0], (a, b)
+            assert (L, op) == (want[(a, b)][0], want[(a, b)][2]), (a, b)
             assert L > 500 and (sp, sq) == (a, b)
             assert np.array_equal(seqs[a][op:op + L], seqs[b][oq:oq + L]), (a, b)
             assert op == first_shared_window(seqs[a], seqs[b], L), (a, b)
