@@ -73,6 +73,14 @@ __device__ __forceinline__ uint32_t extend(const CH *__restrict__ t, uint32_t n,
     return h;
 }
 
+// A step of a wave takes 64 consecutive positions, one per lane. When
+// Phi[i] = Phi[i-1] + 1 and PLCP[i-1] >= 1, then PLCP[i] = PLCP[i-1] - 1
+// exactly (both suffixes lose the same first symbol), so a run of such
+// positions follows from the PLCP at its head with no text read: only heads
+// compare text (Kasai's bound, from the lane's previous step), then every
+// lane of a run takes head - distance by a wave-wide segmented propagation
+// (the run may continue from the previous step's last lane). A run whose head
+// value drops to 0 before its end leaves the rest to compare for themselves.
 template <typename CH>
 __global__ __launch_bounds__(kBlock) void k_plcp(const CH *__restrict__ t, uint32_t n,
                                                  const int2 *__restrict__ isa_phi, int32_t *__restrict__ plcp,
@@ -80,20 +88,40 @@ __global__ __launch_bounds__(kBlock) void k_plcp(const CH *__restrict__ t, uint3
     const uint32_t span = kWave * steps;
     const uint32_t waves = (n + span - 1) / span;
     const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t below = lane ? (~0ull >> (64u - lane)) : 0ull;   // lanes under this one
     for (uint32_t w = (blockIdx.x * kBlock + threadIdx.x) / kWave; w < waves; w += gridDim.x * (kBlock / kWave)) {
-        uint32_t h = 0;
-        for (uint32_t k = 0, i = w * span + lane; k < steps && i < n; ++k, i += kWave) {
-            const int2 q = isa_phi[i];
-            isa_out[i] = q.x;
-            const int32_t j = q.y;
-            if (j < 0 || (uint32_t)j >= n) {
-                plcp[i] = 0;
-                h = 0;
-                continue;
+        uint32_t h = 0;                                    // Kasai bound from this lane's previous step
+        uint32_t prev_j = 0xffffffffu, prev_p = 0;         // Phi and PLCP of the position before lane 0
+        for (uint32_t k = 0, i0 = w * span; k < steps && i0 < n; ++k, i0 += kWave) {
+            const uint32_t i = i0 + lane;
+            const bool valid = i < n;
+            uint32_t j = 0xffffffffu;
+            if (valid) {
+                const int2 q = isa_phi[i];
+                isa_out[i] = q.x;
+                j = (uint32_t)q.y;                           // n or more: no predecessor (rank 0)
             }
-            h = extend(t, n, i, (uint32_t)j, h, wide != 0);
-            plcp[i] = (int32_t)h;
-            h = h > kWave ? h - kWave : 0;
+            const bool has = valid && j < n;
+            uint32_t jl = (uint32_t)__shfl_up((int)j, 1, kWave);
+            if (lane == 0) jl = prev_j;
+            const bool chained = has && j > 0 && jl < n && jl == j - 1;
+            uint32_t p = 0;
+            if (has && !chained) p = extend(t, n, i, j, h, wide != 0);
+            // segment heads: every lane not chained to the one before it
+            const uint64_t starts = __ballot(!chained);
+            const uint64_t mine = starts & (below | (1ull << lane));
+            const int head = mine ? 63 - __builtin_clzll(mine) : -1;
+            const uint32_t hv = (uint32_t)__shfl((int)p, head < 0 ? 0 : head, kWave);
+            const uint32_t H = head < 0 ? prev_p : hv;
+            const uint32_t d = head < 0 ? lane + 1u : lane - (uint32_t)head;
+            if (chained) {
+                if (H >= d) p = H - d;
+                else p = extend(t, n, i, j, h, wide != 0);   // the run reached 0 before this lane
+            }
+            if (valid) plcp[i] = (int32_t)p;
+            h = p > kWave ? p - kWave : 0;
+            prev_j = (uint32_t)__shfl((int)j, 63, kWave);
+            prev_p = (uint32_t)__shfl((int)p, 63, kWave);
         }
     }
 }
