@@ -18,7 +18,10 @@ follow-up suffix-pair lcp queries) arrive over time. The loop
   (workspace, inputs, outputs, and the resident state of its keep-state
   requests) against the budget, and counts the times admission had to wait
   for memory;
-* records arrival-to-result latency per request and per follow-up batch.
+* records arrival-to-result latency per request and per follow-up batch;
+* keeps serving when a call fails (for instance a base outside 0..3): a
+  failed batch of several requests is retried one request at a time, and
+  only a request that fails alone is marked failed (its error kept).
 
 With batching off every request runs alone on the plain path (SA, LCP,
 overlap scan). All GPU work goes through the C-ABI (paper_1404_3448_amd.lor);
@@ -55,6 +58,7 @@ class Request:
     t_followup_arrival: float | None = None
     batched: bool = False
     rejected: bool = False
+    error: str | None = None          # why the request (or its follow-up batch) failed
 
     @property
     def bases(self) -> int:
@@ -247,6 +251,7 @@ class Server:
         """Serve `requests` (arrival times in seconds) in real time. Returns stats."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         queue = []            # arrived requests, oldest first
+        solo = []             # requests of a failed batch, each to be retried alone
         followups = []        # follow-up batches that are due, oldest first
         timers = []           # (time, seq, request) follow-ups becoming due
         running = {}
@@ -279,6 +284,15 @@ class Server:
             nonlocal blocked
             if followups:
                 return "followup", [followups.pop(0)], 0
+            while solo:
+                kind = "batch" if self.batching else "plain"
+                nbytes = self._item_bytes(kind, solo[:1])
+                if nbytes > self.budget:
+                    reject(solo.pop(0), t)
+                    continue
+                if self.in_use + nbytes > self.budget:
+                    return None
+                return kind, [solo.pop(0)], nbytes
             while queue:
                 kind = "batch" if self.batching else "plain"
                 first = self._item_bytes(kind, queue[:1])
@@ -338,9 +352,28 @@ class Server:
                 finished = [f for f in running if f.done()]
                 for f in finished:
                     kind, group, nbytes = running.pop(f)
-                    res = f.result()
+                    err = f.exception()
+                    res = None if err is not None else f.result()
                     t_end = now()
                     self.in_use -= nbytes
+                    if err is not None:
+                        if kind == "followup":
+                            r = group[0]
+                            r.error = f"follow-up: {err}"
+                            r.t_followup = t_end
+                            self.state.pop(r.rid, None)
+                            self.in_use -= resident_bytes(r.bases)
+                            fol_done += 1
+                        elif len(group) > 1:
+                            solo.extend(group)          # find the request that fails
+                        else:
+                            r = group[0]
+                            r.error = str(err)
+                            r.t_result = t_end
+                            done += 1
+                            if r.keep and r.followup is not None:
+                                fol_total -= 1
+                        continue
                     if kind == "followup":
                         r = group[0]
                         r.followup_result = res
@@ -365,14 +398,16 @@ class Server:
         finally:
             pool.shutdown(wait=True)
         wall = now()
-        served = [r for r in reqs if not r.rejected]
+        served = [r for r in reqs if not r.rejected and r.error is None]
         lat = np.array([r.t_result - r.arrival for r in served]) * 1e3
         flat = np.array([r.t_followup - r.t_followup_arrival for r in reqs if r.t_followup is not None]) * 1e3
         nq = sum(r.followup[0].size for r in reqs if r.t_followup is not None)
         # time to the last pair result (the run itself also waits for follow-up batches)
         rspan = max((r.t_result for r in served), default=0.0) - (reqs[0].arrival if reqs else 0.0)
         return {
-            "requests": total, "rejected": total - len(served), "wall_s": round(wall, 3),
+            "requests": total, "rejected": sum(r.rejected for r in reqs),
+            "failed": sum(r.error is not None and not r.rejected and r.result is None for r in reqs),
+            "wall_s": round(wall, 3),
             "pairs_per_s": round(len(served) / wall, 1) if wall > 0 else None,
             "results_s": round(rspan, 4),
             "result_pairs_per_s": round(len(served) / rspan, 1) if rspan > 0 else None,

@@ -55,3 +55,19 @@ def test_alone_equals_mix_under_memory_pressure():
         assert r.result == ov, r.rid
         if r.keep:
             assert np.array_equal(r.followup_result, fol), r.rid
+
+
+def test_bad_request_fails_alone_on_the_gpu():
+    reqs = serve.make_requests(seed=9, count=12, qps=1e9, lo=2e4, hi=1e5, queries=500, followup_mean=0.002)
+    bad = reqs[5]
+    bad.a = bad.a.copy()
+    bad.a[bad.a.size // 2] = 7                  # not a base
+    srv = serve.Server(slots=2, batch_max=6)
+    stats = srv.run(reqs)
+    assert stats["failed"] == 1 and bad.result is None and "status 2" in bad.error
+    for r in reqs:
+        if r is not bad:
+            ov, fol = alone(r)
+            assert r.result == ov, r.rid
+            if r.keep:
+                assert np.array_equal(r.followup_result, fol), r.rid

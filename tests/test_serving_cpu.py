@@ -99,3 +99,35 @@ def test_byte_accounting_matches_size_queries():
     assert serve.plain_bytes(1000, False) == 1000 + n + 8 * n + ws
     assert serve.plain_bytes(1000, True) - serve.plain_bytes(1000, False) == 4 * n + lor.lor_rmq_compact_bytes(n)
     assert serve.resident_bytes(1000) == 8 * n + lor.lor_rmq_compact_bytes(n)
+
+
+class FailingRunner(FakeRunner):
+    """Fails every call whose requests include `bad`."""
+
+    def __init__(self, bad):
+        super().__init__()
+        self.bad = bad
+
+    def batch(self, reqs):
+        if any(r.rid == self.bad for r in reqs):
+            with self.lock:
+                self.calls.append(("fail", tuple(r.rid for r in reqs)))
+            raise RuntimeError("lor_longest_overlap_batched: status 2 (base outside A,C,G,T (0..3))")
+        return super().batch(reqs)
+
+
+def test_a_failing_request_fails_alone():
+    reqs = [mk(i, 3000, 2000, 0.0, keep=(i % 4 == 0)) for i in range(24)]
+    runner = FailingRunner(bad=9)
+    srv = serve.Server(runner=runner, slots=2, batch_max=8)
+    stats = srv.run(reqs)
+    assert stats["failed"] == 1 and stats["rejected"] == 0
+    assert reqs[9].result is None and "status 2" in reqs[9].error
+    for r in reqs:
+        if r.rid != 9:
+            assert r.result == ("batch", r.rid) and r.error is None
+            if r.keep:
+                assert np.all(r.followup_result == r.rid)
+    fails = [c[1] for c in runner.calls if c[0] == "fail"]
+    assert len(fails) == 2 and fails[-1] == (9,)     # the batch, then request 9 alone
+    assert srv.in_use == 0 and not srv.state
