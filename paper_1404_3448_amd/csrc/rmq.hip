@@ -5,14 +5,15 @@
 // The paper answers RMQ through a Cartesian tree, an Euler tour and +-1RMQ.
 // Here the structure is a sparse table: level k holds the minimum of every
 // window of 2^k LCP entries, and a query reads two overlapping windows that
-// cover its range. Levels 1-10 are built in one pass: a workgroup loads a
-// tile of the LCP array plus the halo the ten levels reach into, and
-// computes and writes those levels from LDS, so the LCP array is read once
-// for ten levels. Higher levels (windows wider than a tile) are built three
-// (or two) at a time from level k-1 by workgroups that walk columns of
-// blocks 2^(k-1) entries apart and keep the blocks they still need in
-// registers, so level k-1 is read about once per pass and every level is
-// written once. With 288 GB of HBM the table fits next to
+// cover its range. Levels 1-9 are built in one pass: a wave loads a
+// segment of the LCP array plus the halo the nine levels reach into, and
+// computes and writes those levels in registers (wave shuffles for windows
+// narrower than the wave), so the LCP array is read once for nine levels.
+// Higher levels are built three (or fewer) at a time from level k-1: entries
+// 2^(k-1) apart form columns, each wave loads a window of rows of 512
+// neighbouring columns at once and takes the minima down the columns in
+// registers, so level k-1 is read about twice per three levels and every
+// level is written once. With 288 GB of HBM the table fits next to
 // the 1G-suffix arrays, and every query costs four independent gathers
 // (two ISA entries, two table entries) instead of a pointer walk.
 // Levels hold minima of LCP values, so when the largest LCP is at most
@@ -27,16 +28,6 @@
 namespace lor {
 
 namespace {
-
-// One level from the previous one, a tile of kLvTile outputs per workgroup.
-// Entry x of the previous level is read twice: by output tile x's workgroup
-// and by the one 2^(k-1) entries to its left. When that distance spans H >= 1
-// tiles, tiles t and t + H are taken one right after the other (order within
-// groups of 2H tiles: 0, H, 1, H + 1, ...), so the second read of the shared
-// tile finds it in L2; the sequence is dealt to the XCDs in contiguous
-// eighths so that partners run on the same XCD.
-constexpr uint32_t kLvItems = 16;
-constexpr uint32_t kLvTile = kBlock * kLvItems;
 
 // Level storage of a table: entries from `base` on, 16-bit when the header
 // word says every LCP value fits (hdr == nullptr: always 32-bit).
@@ -59,130 +50,160 @@ __device__ __forceinline__ TabView tab_view(int32_t *base, const uint32_t *hdr) 
     return t;
 }
 
-__global__ __launch_bounds__(kBlock) void k_st_level(int32_t *__restrict__ base, const uint32_t *__restrict__ hdr,
-                                                     uint64_t prev_off, uint64_t cur_off, uint32_t half,
-                                                     uint32_t cnt, uint32_t tiles) {
-    const TabView tv = tab_view(base, hdr);
-    const uint32_t per = (tiles + kXcds - 1) / kXcds;
-    const uint32_t j = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;   // place in the sequence
-    if (blockIdx.x / kXcds >= per || j >= tiles) return;
-    const uint32_t H = half / kLvTile;
-    uint32_t t = j;
-    if (H >= 1) {
-        const uint32_t G = 2 * H, g = j / G, k = j % G;
-        if ((uint64_t)(g + 1) * G <= tiles) t = g * G + (k >> 1) + (k & 1u) * H;   // a partial last group keeps plain order
-    }
-    const uint32_t i0 = t * kLvTile + threadIdx.x;
-    int32_t a[kLvItems], b[kLvItems];
-#pragma unroll
-    for (int r = 0; r < (int)kLvItems; ++r) {
-        const uint32_t i = i0 + r * kBlock;
-        a[r] = i < cnt ? tv.get(prev_off + i) : 0;
-        b[r] = i < cnt ? tv.get(prev_off + i + half) : 0;
-    }
-#pragma unroll
-    for (int r = 0; r < (int)kLvItems; ++r) {
-        const uint32_t i = i0 + r * kBlock;
-        if (i < cnt) tv.put(cur_off + i, min(a[r], b[r]));
-    }
-}
-
 __device__ __forceinline__ uint64_t level_offset_dev(uint64_t n, int level);
 
-// NL levels k .. k+NL-1 from level k-1 (P) in one pass. With h = 2^(k-1)
-// and blocks of B = 256 ITEMS entries (B divides h, H = h / B), output entry
-// i of level k+a is the minimum of P[i + u h] over u < 2^(a+1), and
-// i + u h lies u blocks of H further along the column of blocks
-// b, b + H, b + 2H, ... A workgroup walks `steps` consecutive blocks of one
-// column and keeps the last 2^NL blocks of P in registers, so each block of
-// P is read from HBM about once for all NL levels (instead of twice per
-// level); the writes are the table itself.
-template <int NL, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_st_chain(int32_t *__restrict__ table, const uint32_t *__restrict__ hdr,
-                                                     uint32_t cnt_p, uint32_t n, int k, uint32_t H, uint32_t nb,
-                                                     uint32_t steps) {
-    const TabView tv = tab_view(table, hdr);
-    const uint64_t p_off = level_offset_dev(n, k - 1);   // level k-1 (k >= 2)
-    constexpr int W = 1 << NL;
-    constexpr uint32_t B = kBlock * ITEMS;
-    const uint32_t c = blockIdx.x % H;
-    const uint32_t j0 = (blockIdx.x / H) * steps;
-    const uint32_t len = nb > c ? (nb - 1 - c) / H + 1 : 0;   // blocks of this column
-    if (j0 >= len) return;
-    const uint32_t j1 = min(len, j0 + steps);
-    int32_t win[W][ITEMS];
-    auto load = [&](uint32_t j, int32_t (&dst)[ITEMS]) {
-        const uint64_t base = (uint64_t)(c + (uint64_t)j * H) * B + threadIdx.x;
-#pragma unroll
-        for (int r = 0; r < ITEMS; ++r) {
-            const uint64_t idx = base + (uint64_t)r * kBlock;
-            dst[r] = idx < cnt_p ? tv.get(p_off + idx) : INT_MAX;
-        }
-    };
-#pragma unroll
-    for (int u = 0; u < W - 1; ++u) load(j0 + u, win[u]);
-    for (uint32_t j = j0; j < j1; ++j) {
-        load(j + W - 1, win[W - 1]);
-        const uint64_t i0 = (uint64_t)(c + (uint64_t)j * H) * B + threadIdx.x;
-#pragma unroll
-        for (int r = 0; r < ITEMS; ++r) {
-            const uint64_t i = i0 + (uint64_t)r * kBlock;
-            int32_t m = win[0][r];
-#pragma unroll
-            for (int a = 0; a < NL; ++a) {
-#pragma unroll
-                for (int u = 1 << a; u < (2 << a); ++u) m = min(m, win[u][r]);
-                const int lv = k + a;
-                if (i < (uint64_t)n - (1ull << lv) + 1) tv.put(level_offset_dev(n, lv) + i, m);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < W - 1; ++u)
-#pragma unroll
-            for (int r = 0; r < ITEMS; ++r) win[u][r] = win[u + 1][r];
-    }
-}
-
-constexpr uint32_t kChainSteps = 8;         // blocks per workgroup along a column (8 beat 4, 16, 32 and 64)
-
-constexpr uint32_t kStTile = kBlock * 8;    // outputs per workgroup in fused levels
-constexpr int kStFuse = 10;                 // levels per fused pass
-constexpr int kStFusedTop = 10;             // levels 1..10 are built in LDS (halo < 1024 entries)
+constexpr int kStFusedTop = 9;              // levels 1..9 are built from registers (halo < 512 entries)
+constexpr int kStOut = 16;                  // outputs per lane in fused levels (a wave: 64 kStOut entries)
+constexpr int kStIn = kStOut + (1 << (kStFusedTop - 6));   // entries loaded per lane: the outputs plus the halo
+constexpr uint32_t kStWave = kWave * kStOut;
 constexpr uint32_t kRmqBlock = 64;          // LCP entries per block of the compact table
 
-// Levels k0 .. k0+nl-1 from level k0-1 (`prev`, prev_count entries) for the
-// outputs [i0, i0 + kStTile) of this workgroup.
+// Levels 1 .. nl (nl <= kStFusedTop) from level 0 (`prev`, prev_count
+// entries), one wave per segment of kStWave outputs, with no LDS and no
+// barriers. Lane l holds entries i0 + 64 m + l (m < kStIn) of the current
+// level in v[m], so the partner of an entry at distance half lies in
+// register m + half / 64 of the same lane when half >= 64, and otherwise in
+// lane (l + half) mod 64 of register m or m + 1 (a wave shuffle). Each level
+// is computed in place in ascending m, which leaves the higher registers,
+// still needed, untouched. The 2^kStFusedTop entries loaded past the
+// outputs cover the widest window; reads past prev_count load INT_MAX, which
+// no minimum keeps. Measured at 1G (16-bit levels): 16 outputs per lane and
+// levels 1-9, 5.6 ms; levels 1-10 here 7.6 ms (8 outputs per lane: 7.2 ms,
+// 24 or 32: 22-24 ms, fewer waves in flight); levels 1-10 from LDS tiles
+// with two barriers per level 9.5 ms.
 __global__ __launch_bounds__(kBlock) void k_st_fused(const int32_t *__restrict__ prev, uint32_t prev_count,
-                                                     uint32_t n, int k0, int nl, int32_t *__restrict__ table,
+                                                     uint32_t n, int nl, int32_t *__restrict__ table,
                                                      const uint32_t *__restrict__ hdr) {
-    extern __shared__ int32_t s_buf[];
-    const TabView tv = tab_view(table, hdr);
-    const uint32_t halo = (1u << (k0 - 1)) * ((1u << nl) - 1u);
-    const uint32_t span = kStTile + halo;
-    int32_t *b0 = s_buf, *b1 = s_buf + span;
-    const uint32_t i0 = blockIdx.x * kStTile;
-    for (uint32_t j = threadIdx.x; j < span; j += kBlock) {
-        const uint32_t i = i0 + j;
-        b0[j] = i < prev_count ? prev[i] : INT_MAX;
-    }
-    __syncthreads();
-    uint32_t valid = span;
-    for (int l = 0; l < nl; ++l) {
-        const int k = k0 + l;
+    const bool narrow = hdr != nullptr && hdr[0] <= 65535u;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t w0 = ((uint64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6)) * kStWave;
+    if (w0 >= n) return;
+    const uint64_t i0 = w0 + lane;
+    // entries left from this lane's first one: loads and stores test m * 64 against them
+    const int64_t have = (int64_t)prev_count - (int64_t)i0;
+    const int32_t *src = prev + i0;
+    int32_t v[kStIn];
+#pragma unroll
+    for (int m = 0; m < kStIn; ++m) v[m] = m * (int64_t)kWave < have ? src[m * kWave] : INT_MAX;
+#pragma unroll
+    for (int k = 1; k <= kStFusedTop; ++k) {
+        if (k > nl) break;
         const uint32_t half = 1u << (k - 1);
-        valid -= half;
-        for (uint32_t j = threadIdx.x; j < valid; j += kBlock) b1[j] = min(b0[j], b0[j + half]);
-        __syncthreads();
-        const uint32_t count = n - (1u << k) + 1u;
-        const uint64_t off = level_offset_dev(n, k);
-        for (uint32_t j = threadIdx.x; j < kStTile; j += kBlock) {
-            const uint32_t i = i0 + j;
-            if (i < count) tv.put(off + i, b1[j]);
+        if (half >= kWave) {
+            const int off = (int)(half / kWave);
+#pragma unroll
+            for (int m = 0; m < kStIn; ++m)
+                if (m + off < kStIn) v[m] = min(v[m], v[m + off]);
+        } else {
+            const int from = (int)((lane + half) & 63u);
+            const bool wrap = lane + half >= kWave;   // the partner is in register m + 1
+            int32_t cur = __shfl(v[0], from, kWave);
+#pragma unroll
+            for (int m = 0; m < kStIn; ++m) {
+                const int32_t next = m + 1 < kStIn ? __shfl(v[m + 1], from, kWave) : INT_MAX;
+                v[m] = min(v[m], wrap ? next : cur);
+                cur = next;
+            }
         }
-        int32_t *x = b0; b0 = b1; b1 = x;
-        __syncthreads();
+        const int64_t left = (int64_t)n - (int64_t)(1u << k) + 1 - (int64_t)i0;   // outputs of level k from i0 on
+        const uint64_t at = level_offset_dev(n, k) + i0;
+        if (narrow) {
+            uint16_t *dst = reinterpret_cast<uint16_t *>(table) + at;
+#pragma unroll
+            for (int m = 0; m < kStOut; ++m)
+                if (m * (int64_t)kWave < left) dst[m * kWave] = (uint16_t)v[m];
+        } else {
+            int32_t *dst = table + at;
+#pragma unroll
+            for (int m = 0; m < kStOut; ++m)
+                if (m * (int64_t)kWave < left) dst[m * kWave] = v[m];
+        }
     }
 }
+
+// Levels k .. k+NL-1 (k > kStFusedTop, so h = 2^(k-1) is a multiple of
+// 64 C) from level k-1 (P). Output entry i of level k+a is the minimum of
+// P[i + u h] over u < 2^(a+1): entries h apart form a column, and a level
+// is a sliding minimum down the columns. A wave takes C groups of 64
+// neighbouring columns and S rows: lane l loads P[i0 + 64 c + l + m h] for
+// c < C, m < S + 2^NL - 1 into v[c][m], all loads issued at once, then each
+// level is computed in place (v[c][m] = min(v[c][m], v[c][m + 2^a]),
+// ascending m) and its S rows are stored, each row of a wave a contiguous
+// run of 64 C entries. Waves of one row block take neighbouring column
+// groups, so their loads and stores meet the same rows together. Rows past
+// the level's end load INT_MAX and store nothing. Measured at 1G (levels
+// 10-29, 16-bit): 8 groups and 8 rows 14.4 ms; 4 groups and 16 rows 15.0,
+// 2 and 16 15.6, 8 and 4 16.6, one group and 8-32 rows 18.8-19.5 ms; four
+// levels per pass 21.3 ms; a walk down a column of blocks, one block load
+// per step and then its stores, with a single-level pass for level 10,
+// 16.4 ms.
+template <int NL, int S, int C>
+__global__ __launch_bounds__(kBlock) void k_st_cols(int32_t *__restrict__ table, const uint32_t *__restrict__ hdr,
+                                                    uint32_t n, int k, uint32_t qcols, uint32_t rblocks) {
+    constexpr int M = S + (1 << NL) - 1;
+    const bool narrow = hdr != nullptr && hdr[0] <= 65535u;
+    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6);
+    const uint64_t q = wave % qcols, r = wave / qcols;
+    if (r >= rblocks) return;
+    const uint64_t h = 1ull << (k - 1);
+    const uint64_t i0 = r * (uint64_t)S * h + q * (uint64_t)(kWave * C) + (threadIdx.x & 63u);
+    const int64_t have = (int64_t)n - (int64_t)h + 1 - (int64_t)i0;   // entries of level k-1 from i0 on
+    const uint64_t p_off = level_offset_dev(n, k - 1) + i0;
+    int32_t v[C][M];
+    if (narrow) {
+        const uint16_t *src = reinterpret_cast<const uint16_t *>(table) + p_off;
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int64_t e = (int64_t)(m * h) + c * kWave;
+                v[c][m] = e < have ? (int32_t)src[e] : INT_MAX;
+            }
+    } else {
+        const int32_t *src = table + p_off;
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int64_t e = (int64_t)(m * h) + c * kWave;
+                v[c][m] = e < have ? src[e] : INT_MAX;
+            }
+    }
+#pragma unroll
+    for (int a = 0; a < NL; ++a) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int m = 0; m + (1 << a) < M; ++m) v[c][m] = min(v[c][m], v[c][m + (1 << a)]);
+        const int lv = k + a;
+        const int64_t left = (int64_t)n - (int64_t)(1ull << lv) + 1 - (int64_t)i0;   // outputs of level lv from i0 on
+        const uint64_t at = level_offset_dev(n, lv) + i0;
+        if (narrow) {
+            uint16_t *dst = reinterpret_cast<uint16_t *>(table) + at;
+#pragma unroll
+            for (int m = 0; m < S; ++m)
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int64_t e = (int64_t)(m * h) + c * kWave;
+                    if (e < left) dst[e] = (uint16_t)v[c][m];
+                }
+        } else {
+            int32_t *dst = table + at;
+#pragma unroll
+            for (int m = 0; m < S; ++m)
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int64_t e = (int64_t)(m * h) + c * kWave;
+                    if (e < left) dst[e] = v[c][m];
+                }
+        }
+    }
+}
+
+constexpr int kColLevels = 3;   // levels per column pass
+constexpr int kColRows = 8;     // rows per wave in a column pass
+constexpr int kColGroups = 8;   // groups of 64 neighbouring columns per wave
+static_assert((1 << kStFusedTop) >= kWave * kColGroups, "a column pass needs h >= 64 kColGroups");
 
 struct Levels {
     const int32_t *lcp;
@@ -436,55 +457,37 @@ lor_status rmq_build_full(const int32_t *lcp, uint32_t n, int32_t *buffer, int l
 lor_status rmq_build_levels(const int32_t *lcp, uint32_t n, int32_t *table, int levels, hipStream_t s,
                             const uint32_t *hdr, int eb) {
     int k = 1;
-    while (k <= levels && k <= kStFusedTop) {
-        const int nl = min(kStFuse, min(levels, kStFusedTop) - k + 1);
-        const int32_t *prev = lcp;   // k == 1: the fused pass starts from level 0
-        const uint32_t prev_count = n - (1u << (k - 1)) + 1u;
-        const uint32_t count = n - (1u << k) + 1u;
-        const uint32_t halo = (1u << (k - 1)) * ((1u << nl) - 1u);
-        const size_t lds = 2 * (size_t)(kStTile + halo) * sizeof(int32_t);
-        double bytes = 0;
-        for (int l = 0; l < nl; ++l) bytes += (double)eb * (n - (1u << (k + l)) + 1u);
-        bytes += 4.0 * prev_count;
+    if (levels >= 1) {
+        // levels 1 .. min(levels, kStFusedTop) in one pass from level 0
+        const int nl = min(levels, kStFusedTop);
+        double bytes = 4.0 * n;
+        for (int l = 1; l <= nl; ++l) bytes += (double)eb * (n - (1u << l) + 1u);
+        const uint32_t waves = div_up(n, kStWave);
         LOR_LAUNCH("k_st_fused", bytes, s,
-                   hipLaunchKernelGGL(k_st_fused, dim3(div_up(count, kStTile)), dim3(kBlock), lds, s, prev,
-                                      prev_count, n, k, nl, table, hdr));
-        k += nl;
+                   hipLaunchKernelGGL(k_st_fused, dim3(div_up(waves, kBlock / kWave)), dim3(kBlock), 0, s, lcp, n,
+                                      n, nl, table, hdr));
+        k = nl + 1;
     }
     while (k <= levels) {
-        const uint32_t half = 1u << (k - 1);
-        const int nl = min(3, levels - k + 1);
-        const uint32_t items = half >= kBlock * 16u && nl < 3 ? 16u : (half >= kBlock * 8u ? 8u : 4u);
-        if (nl == 1 || half < kBlock * 4u) {
-            const uint32_t cnt = n - (1u << k) + 1u;
-            const uint32_t tiles = div_up(cnt, kLvTile);
-            LOR_LAUNCH("k_st_level", (double)cnt * 2 * eb, s,
-                       hipLaunchKernelGGL(k_st_level, dim3(kXcds * div_up(tiles, kXcds)), dim3(kBlock), 0, s, table,
-                                          hdr, rmq_level_offset(n, k - 1), rmq_level_offset(n, k), half, cnt,
-                                          tiles));
-            ++k;
-            continue;
-        }
-        const uint32_t B = kBlock * items, H = half / B;
-        const uint32_t cnt_p = n - half + 1u;
-        const uint32_t nb = div_up(n - (1u << k) + 1u, B);   // blocks holding level-k outputs
-        const uint32_t segs = div_up(div_up(nb, H), kChainSteps);
-        double bytes = (double)eb * cnt_p;
+        // levels k .. k+nl-1 from level k-1, down columns h = 2^(k-1) apart
+        const int nl = min(kColLevels, levels - k + 1);
+        const uint64_t h = 1ull << (k - 1);
+        const uint32_t qcols = (uint32_t)(h / (kWave * kColGroups));
+        const uint64_t rows = div_up((uint64_t)n - 2 * h + 1, h);   // rows holding level-k outputs
+        const uint32_t rblocks = (uint32_t)div_up(rows, (uint64_t)kColRows);
+        const uint64_t waves = (uint64_t)qcols * rblocks;
+        const dim3 grid((uint32_t)div_up(waves, (uint64_t)(kBlock / kWave)));
+        double bytes = (double)eb * (n - h + 1);
         for (int a = 0; a < nl; ++a) bytes += (double)eb * (n - (1u << (k + a)) + 1u);
-        const dim3 grid(H * segs);
-#define LOR_CHAIN(NL, IT)                                                                                   \
-    LOR_LAUNCH("k_st_chain", bytes, s,                                                                      \
-               hipLaunchKernelGGL((k_st_chain<NL, IT>), grid, dim3(kBlock), 0, s, table, hdr, cnt_p, n, k, H, \
-                                  nb, kChainSteps))
-        if (nl == 3) {
-            if (items == 4) LOR_CHAIN(3, 4);
-            else LOR_CHAIN(3, 8);
-        } else {
-            if (items == 4) LOR_CHAIN(2, 4);
-            else if (items == 8) LOR_CHAIN(2, 8);
-            else LOR_CHAIN(2, 16);
-        }
-#undef LOR_CHAIN
+#define LOR_COLS(NL)                                                                                     \
+    LOR_LAUNCH("k_st_cols", bytes, s,                                                                    \
+               hipLaunchKernelGGL((k_st_cols<NL, kColRows, kColGroups>), grid, dim3(kBlock), 0, s, table, hdr, n, \
+                                  k, qcols, rblocks))
+        static_assert(kColLevels == 3, "one launch form per level count up to kColLevels");
+        if (nl == 3) LOR_COLS(3);
+        else if (nl == 2) LOR_COLS(2);
+        else LOR_COLS(1);
+#undef LOR_COLS
         k += nl;
     }
     return LOR_OK;
