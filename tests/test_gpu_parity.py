@@ -451,6 +451,40 @@ def test_rmq_table_width_boundary(top):
     assert (host(whole[0])[0], host(whole[1])[0]) == oracle.range_min(lcp_h, 0, n - 1)
 
 
+@pytest.mark.parametrize("n", [1500, 2049, 4095, 5000, 9000, 20000, 33000])
+@pytest.mark.parametrize("top", [1000, 100000])
+def test_rmq_every_level_count(n, top):
+    """Tables of 10 to 15 levels in 16- and 32-bit entries: the level passes
+    above the register pass take three levels at a time, so these sizes end
+    with a pass of one, two or three levels. For every level k, ranges of
+    exactly 2^k entries and of 2^k + 1 .. 2^(k+1) - 1 entries, at random
+    starts and flush with both ends, answer as the plain minimum does, with
+    the leftmost position; smooth values with noise make ties rare and every
+    window's minimum depend on where it lies."""
+    say("rmq levels", n, top)
+    rng = np.random.default_rng(n + top)
+    x = np.arange(n)
+    lcp_h = (top / 2 + top / 3 * np.sin(x / 97.0) + rng.integers(0, max(2, top // 50), size=n)).astype(np.int32)
+    lcp_h[rng.integers(0, n)] = top
+    lcp = dev(lcp_h)
+    rmq = lor.lor_rmq_build(lcp)
+    levels = n.bit_length() - 1
+    assert rmq.levels == levels
+    lo, hi = [], []
+    for k in range(levels + 1):
+        w = 1 << k
+        for span in (w, min(n, w + 1 + int(rng.integers(0, w))), min(n, 2 * w - 1)):
+            for start in (0, n - span, *rng.integers(0, n - span + 1, size=6)):
+                lo.append(int(start))
+                hi.append(int(start) + span - 1)
+    lo, hi = np.array(lo), np.array(hi)
+    m, a = lor.lor_rmq_query(rmq, lcp, None, 0, dev(lo.astype(np.int32)), dev(hi.astype(np.int32)),
+                             want_argmin=True)
+    m, a = host(m), host(a)
+    for q in range(lo.size):
+        assert (m[q], a[q]) == oracle.range_min(lcp_h, lo[q], hi[q]), (q, lo[q], hi[q])
+
+
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 127, 128, 129, 191, 1000, 4097, 100003])
 @pytest.mark.parametrize("values", [2, 50, 1 << 20])
 def test_rmq_compact_equals_oracle_and_full_table(n, values):
